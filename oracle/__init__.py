@@ -1,0 +1,239 @@
+"""Python face of the CPU oracle (``libccmg_oracle.so``, plain C, FP64).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only users.  The solver package never imports this.
+
+Every function works on numpy arrays laid out [nz][ny][nx] (x fastest) and
+mirrors one step of the cell-centered multigrid method of Bartuschat & Ruede
+(arXiv:1410.6609); the C source cites the section each step follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = [os.path.join(_HERE, "ccmg_oracle.c"), os.path.join(_HERE, "levelops.inc")]
+LIB_PATH = os.path.join(_HERE, "libccmg_oracle.so")
+
+OK, E_ARG, E_NONFINITE, E_NOCONV = 0, -1, -5, -6
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FP contraction, OpenMP)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-shared", "-fPIC", "-Wall", "-Wno-unknown-pragmas", "-Wno-unused-function", "-o", tmp, _SRC[0], "-lm"]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lp = ctypes.POINTER(ctypes.c_longlong)
+        I, D = ctypes.c_int, ctypes.c_double
+        sig = {
+            "or_num_threads": ([], I),
+            "or_set_num_threads": ([I], None),
+            "or_diag_at": ([I, I, I, ip, I, I, I], I),
+            "or_apply": ([I, I, I, D, I, ip, dp, dp], None),
+            "or_residual": ([I, I, I, D, I, ip, dp, dp, dp], None),
+            "or_norm2": ([ctypes.c_longlong, dp], D),
+            "or_rbgs_sweep": ([I, I, I, D, I, ip, dp, dp], None),
+            "or_restrict": ([I, I, I, dp, dp], None),
+            "or_prolong_add": ([I, I, I, dp, D, dp], None),
+            "or_cg": ([I, I, I, D, I, ip, dp, dp, D, I], I),
+            "or_fold": ([I, I, I, D, ip, dp, dp, dp], None),
+            "or_deposit": ([I, I, I, D, I, dp, dp, dp, D, dp, lp], None),
+            "or_dq": ([I, I, I, D, I, dp, dp, D, dp, dp], None),
+            "or_solve": ([I, I, I, D, ip, I, I, I, D, D, I, dp, dp, D, I, dp, ip], I),
+            "or_solve_ir": ([I, I, I, D, ip, I, I, I, D, D, I, I, dp, dp, D, I, dp, ip], I),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _kinds(kinds: Sequence[int]):
+    arr = (ctypes.c_int * 6)(*[int(k) for k in kinds])
+    return arr
+
+
+def _shape(a: np.ndarray) -> Tuple[int, int, int]:
+    nz, ny, nx = a.shape
+    return nx, ny, nz
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().or_set_num_threads(int(n))
+
+
+def diag_at(shape, kinds, i, j, k) -> int:
+    nx, ny, nz = shape
+    return lib().or_diag_at(nx, ny, nz, _kinds(kinds), i, j, k)
+
+
+def apply(phi: np.ndarray, h: float, kinds, level: int = 0) -> np.ndarray:
+    """A_l phi on a level of spacing 2^l h (operator scale 1/(2^l h^2))."""
+    phi = _f64(phi)
+    out = np.empty_like(phi)
+    nx, ny, nz = _shape(phi)
+    lib().or_apply(nx, ny, nz, h, level, _kinds(kinds), _dp(phi), _dp(out))
+    return out
+
+
+def residual(phi, b, h, kinds, level: int = 0) -> np.ndarray:
+    phi, b = _f64(phi), _f64(b)
+    r = np.empty_like(phi)
+    nx, ny, nz = _shape(phi)
+    lib().or_residual(nx, ny, nz, h, level, _kinds(kinds), _dp(phi), _dp(b), _dp(r))
+    return r
+
+
+def norm2(v) -> float:
+    v = _f64(v)
+    return lib().or_norm2(v.size, _dp(v))
+
+
+def rbgs_sweep(phi, b, h, kinds, level: int = 0, sweeps: int = 1) -> np.ndarray:
+    phi = _f64(phi).copy()
+    b = _f64(b)
+    nx, ny, nz = _shape(phi)
+    for _ in range(sweeps):
+        lib().or_rbgs_sweep(nx, ny, nz, h, level, _kinds(kinds), _dp(phi), _dp(b))
+    return phi
+
+
+def restrict(r) -> np.ndarray:
+    r = _f64(r)
+    nx, ny, nz = _shape(r)
+    out = np.empty((nz // 2, ny // 2, nx // 2))
+    lib().or_restrict(nx, ny, nz, _dp(r), _dp(out))
+    return out
+
+
+def prolong_add(phi_fine, e_coarse, omega: float) -> np.ndarray:
+    phi = _f64(phi_fine).copy()
+    e = _f64(e_coarse)
+    nx, ny, nz = _shape(phi)
+    lib().or_prolong_add(nx, ny, nz, _dp(e), omega, _dp(phi))
+    return phi
+
+
+def cg(b, h, kinds, level: int = 0, rtol: float = 1e-13, maxit: Optional[int] = None):
+    b = _f64(b)
+    x = np.zeros_like(b)
+    nx, ny, nz = _shape(b)
+    maxit = 2 * b.size if maxit is None else maxit
+    it = lib().or_cg(nx, ny, nz, h, level, _kinds(kinds), _dp(b), _dp(x), rtol, maxit)
+    return x, it
+
+
+def fold(f, h, kinds, values) -> np.ndarray:
+    f = _f64(f)
+    b = np.empty_like(f)
+    nx, ny, nz = _shape(f)
+    vals = (ctypes.c_double * 6)(*[float(v) for v in values])
+    lib().or_fold(nx, ny, nz, h, _kinds(kinds), vals, _dp(f), _dp(b))
+    return b
+
+
+def deposit(shape, h, centers, radii, q, eps: float = 1.0):
+    """Returns (f = rho/eps [nz][ny][nx], n_s per sphere)."""
+    nx, ny, nz = shape
+    centers, radii, q = _f64(centers).reshape(-1, 3), _f64(radii), _f64(q)
+    n = radii.shape[0]
+    f = np.empty((nz, ny, nx))
+    counts = np.zeros(n, dtype=np.int64)
+    lib().or_deposit(nx, ny, nz, h, n, _dp(centers), _dp(radii), _dp(q), eps, _dp(f),
+                     counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+    return f, counts
+
+
+def dq(lam, h, centers, radii, eps: float = 1.0) -> np.ndarray:
+    lam = _f64(lam)
+    nx, ny, nz = _shape(lam)
+    centers, radii = _f64(centers).reshape(-1, 3), _f64(radii)
+    out = np.zeros(radii.shape[0])
+    lib().or_dq(nx, ny, nz, h, radii.shape[0], _dp(centers), _dp(radii), eps, _dp(lam), _dp(out))
+    return out
+
+
+def default_cg_maxit(shape, levels) -> int:
+    nx, ny, nz = shape
+    d = 1 << (levels - 1)
+    return 2 * (nx // d) * (ny // d) * (nz // d)
+
+
+def solve(b, h, kinds, levels, nu1=2, nu2=2, omega=2.0, rtol=1e-10, max_cycles=100,
+          phi0=None, cg_rtol=1e-13, cg_maxit=None):
+    """FP64 multigrid on the folded RHS b. Returns (phi, history, status)."""
+    b = _f64(b)
+    phi = np.zeros_like(b) if phi0 is None else _f64(phi0).copy()
+    nx, ny, nz = _shape(b)
+    hist = np.zeros(max_cycles + 1)
+    cyc = ctypes.c_int(0)
+    cg_maxit = default_cg_maxit((nx, ny, nz), levels) if cg_maxit is None else cg_maxit
+    st = lib().or_solve(nx, ny, nz, h, _kinds(kinds), levels, nu1, nu2, omega, cg_rtol, cg_maxit,
+                        _dp(b), _dp(phi), rtol, max_cycles, _dp(hist), ctypes.byref(cyc))
+    if st == E_ARG:
+        raise ValueError("oracle: invalid hierarchy")
+    return phi, hist[: cyc.value + 1].copy(), st
+
+
+def solve_ir(b, h, kinds, levels, inner=2, nu1=2, nu2=2, omega=2.0, rtol=1e-10, max_outer=100,
+             phi0=None, cg_rtol=1e-13, cg_maxit=None):
+    """FP32-in-FP64 iterative refinement. Returns (phi, history, status)."""
+    b = _f64(b)
+    phi = np.zeros_like(b) if phi0 is None else _f64(phi0).copy()
+    nx, ny, nz = _shape(b)
+    hist = np.zeros(max_outer + 1)
+    cyc = ctypes.c_int(0)
+    cg_maxit = default_cg_maxit((nx, ny, nz), levels) if cg_maxit is None else cg_maxit
+    st = lib().or_solve_ir(nx, ny, nz, h, _kinds(kinds), levels, nu1, nu2, omega, cg_rtol, cg_maxit,
+                           inner, _dp(b), _dp(phi), rtol, max_outer, _dp(hist), ctypes.byref(cyc))
+    if st == E_ARG:
+        raise ValueError("oracle: invalid hierarchy")
+    return phi, hist[: cyc.value + 1].copy(), st
+
+
+def solve_problem(f, h, kinds, values, levels, **kw):
+    """Fold the boundary conditions into f and solve: the whole forward path."""
+    return solve(fold(f, h, kinds, values), h, kinds, levels, **kw)
+
+
+def adjoint(g, h, kinds, levels, **kw):
+    """lambda = A^{-1} g (A symmetric; homogeneous boundary values)."""
+    return solve(_f64(g), h, kinds, levels, **kw)

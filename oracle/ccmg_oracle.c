@@ -1,0 +1,539 @@
+/*
+ * ccmg_oracle.c -- plain, slow CPU oracle for the cell-centered geometric
+ * multigrid solver of the electric-potential Poisson problem in
+ * D. Bartuschat and U. Ruede, "Parallel Multiphysics Simulations of Charged
+ * Particles in Microfluidic Flows" (arXiv:1410.6609).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the HIP implementation; the two meet only
+ * through seeded inputs.
+ *
+ * What it computes (FP64 unless noted; arrays [nz][ny][nx], x fastest; cell
+ * (i,j,k) has centre ((i+1/2)h, (j+1/2)h, (k+1/2)h)):
+ *   - Poisson's equation -Lap(phi) = rho/eps (Sec. 2.4, Eq. Poisson), finite
+ *     volume 7-point stencil (1/h^2)[6; -1 per face neighbour] (Sec. 2.4).
+ *   - Dirichlet and Neumann boundary conditions folded into stencil and RHS
+ *     at near-boundary cells (Sec. 2.4, "Boundary conditions"), applied
+ *     independently per direction (Sec. 5.3): a Dirichlet face adds +1 to the
+ *     stencil centre and 2 g_d / h^2 to the RHS, a Neumann face (g_n = outward
+ *     normal derivative) adds -1 to the centre and g_n / h to the RHS.
+ *   - Naive volume-mapped charge deposition (Sec. 2.4, "Subsampling"): a cell
+ *     belongs to a sphere if its centre lies in the closed ball; the sphere's
+ *     charge is spread evenly over its cells, rho = q / (n_s h^3).
+ *   - Cell-centered multigrid (Sec. 3, Sec. 5.3): 2x2x2 coarsening, averaging
+ *     restriction, nearest-neighbour prolongation with the coarse correction
+ *     magnified by omega (about 2, Sec. 3), Galerkin coarse operators, which
+ *     for this stencil equal s_l * (integer stencil with the same per-face
+ *     centre entries), s_l = 1/(2^l h^2); red-black Gauss-Seidel smoothing;
+ *     conjugate gradients on the coarsest grid; V(nu1,nu2) cycles repeated
+ *     while the residual L2 norm is not below the tolerance (Alg. 1).
+ *   - FP32-in-FP64 iterative refinement and the adjoint solve with the gradient
+ *     with respect to the sphere charges (extensions of the method; the
+ *     operator is symmetric because folding only changes diagonal entries).
+ *
+ * Parity pins: see the oracle tests.  Per-cycle multigrid iterates are not
+ * printed in the paper, so the cycle itself is pinned only by independent
+ * cross-checks (dense solves, explicit sparse Galerkin cycles, closed forms).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no contraction, so
+ * every operation rounds exactly as written).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_DIRICHLET 0
+#define OR_NEUMANN 1
+#define OR_MAXLEVELS 16
+
+#define OR_OK 0
+#define OR_E_ARG (-1)
+#define OR_E_NONFINITE (-5)
+#define OR_E_NOCONV (-6)
+
+typedef struct {
+    int nx, ny, nz;
+    double s;      /* operator scale 1/(2^l h0^2) */
+    int kind[6];   /* x-, x+, y-, y+, z-, z+ */
+} or_level;
+
+#define IDX(L, i, j, k) ((((size_t)(k)) * (size_t)(L)->ny + (size_t)(j)) * (size_t)(L)->nx + (size_t)(i))
+
+static size_t or_cells(const or_level* L) { return (size_t)L->nx * L->ny * L->nz; }
+
+/* centre entry of the integer stencil: 6, +1 per Dirichlet face of the cell,
+ * -1 per Neumann face (Sec. 2.4: Dirichlet gives beta - alpha, Neumann
+ * beta + alpha with alpha = -1). */
+static int face_shift(int kind) { return kind == OR_DIRICHLET ? 1 : -1; }
+
+static int or_diag(const or_level* L, int i, int j, int k)
+{
+    int d = 6;
+    if (i == 0)         d += face_shift(L->kind[0]);
+    if (i == L->nx - 1) d += face_shift(L->kind[1]);
+    if (j == 0)         d += face_shift(L->kind[2]);
+    if (j == L->ny - 1) d += face_shift(L->kind[3]);
+    if (k == 0)         d += face_shift(L->kind[4]);
+    if (k == L->nz - 1) d += face_shift(L->kind[5]);
+    return d;
+}
+
+static or_level make_level(int nx, int ny, int nz, double h, int level, const int* kinds)
+{
+    or_level L;
+    L.nx = nx; L.ny = ny; L.nz = nz;
+    L.s = 1.0 / (ldexp(1.0, level) * h * h);
+    for (int f = 0; f < 6; ++f) L.kind[f] = kinds[f];
+    return L;
+}
+
+/* ---- the level operations, for double and for float ---------------------- */
+#define REAL double
+#define FN(name) name##_d
+#include "levelops.inc"
+#undef REAL
+#undef FN
+#define REAL float
+#define FN(name) name##_f
+#include "levelops.inc"
+#undef REAL
+#undef FN
+
+static double norm2_d(size_t n, const double* v)
+{
+    double acc = 0.0;
+    for (size_t c = 0; c < n; ++c) acc += v[c] * v[c];
+    return sqrt(acc);
+}
+
+static double dot_d(size_t n, const double* a, const double* b)
+{
+    double acc = 0.0;
+    for (size_t c = 0; c < n; ++c) acc += a[c] * b[c];
+    return acc;
+}
+
+/* Unpreconditioned conjugate gradients on A_l x = b (Sec. 5.3: the coarsest
+ * grid is solved by CG), started from x = 0, stopped when the recursively
+ * updated residual satisfies ||r|| <= rtol ||b|| or after maxit iterations.
+ * Returns the iteration count. */
+static int cg_d(const or_level* L, const double* b, double* x, double rtol, int maxit)
+{
+    const size_t n = or_cells(L);
+    double* r = (double*)malloc(n * sizeof(double));
+    double* p = (double*)malloc(n * sizeof(double));
+    double* q = (double*)malloc(n * sizeof(double));
+    for (size_t c = 0; c < n; ++c) { x[c] = 0.0; r[c] = b[c]; p[c] = b[c]; }
+    const double bnorm = norm2_d(n, b);
+    double rr = dot_d(n, r, r);
+    int it = 0;
+    if (bnorm > 0.0) {
+        while (it < maxit) {
+            apply_d(L, p, q);
+            const double alpha = rr / dot_d(n, p, q);
+            for (size_t c = 0; c < n; ++c) x[c] += alpha * p[c];
+            for (size_t c = 0; c < n; ++c) r[c] -= alpha * q[c];
+            const double rr_new = dot_d(n, r, r);
+            ++it;
+            if (sqrt(rr_new) <= rtol * bnorm) break;
+            const double beta = rr_new / rr;
+            for (size_t c = 0; c < n; ++c) p[c] = r[c] + beta * p[c];
+            rr = rr_new;
+        }
+    }
+    free(r); free(p); free(q);
+    return it;
+}
+
+/* ---- multigrid hierarchy ---------------------------------------------------- */
+typedef struct {
+    int nlev;
+    or_level lev[OR_MAXLEVELS];
+    int nu1, nu2;
+    double omega;
+    double cg_rtol;
+    int cg_maxit;
+    /* per-level storage; level 0 of phi/b belongs to the caller */
+    double* phi[OR_MAXLEVELS];
+    double* b[OR_MAXLEVELS];
+    double* r[OR_MAXLEVELS];
+    float* phif[OR_MAXLEVELS];
+    float* bf[OR_MAXLEVELS];
+    float* rf[OR_MAXLEVELS];
+    int cg_iters_last;
+} or_hier;
+
+static int hier_init(or_hier* H, int nx, int ny, int nz, double h, const int* kinds, int levels,
+                     int nu1, int nu2, double omega, double cg_rtol, int cg_maxit, int want_f32)
+{
+    memset(H, 0, sizeof(*H));
+    if (levels < 1 || levels > OR_MAXLEVELS) return OR_E_ARG;
+    const int div = 1 << (levels - 1);
+    if (nx % div || ny % div || nz % div) return OR_E_ARG;
+    H->nlev = levels; H->nu1 = nu1; H->nu2 = nu2; H->omega = omega;
+    H->cg_rtol = cg_rtol; H->cg_maxit = cg_maxit;
+    for (int l = 0; l < levels; ++l) {
+        H->lev[l] = make_level(nx >> l, ny >> l, nz >> l, h, l, kinds);
+        const size_t n = or_cells(&H->lev[l]);
+        H->r[l] = (double*)calloc(n, sizeof(double));
+        if (l > 0) {
+            H->phi[l] = (double*)calloc(n, sizeof(double));
+            H->b[l] = (double*)calloc(n, sizeof(double));
+        }
+        if (want_f32) {
+            H->phif[l] = (float*)calloc(n, sizeof(float));
+            H->bf[l] = (float*)calloc(n, sizeof(float));
+            H->rf[l] = (float*)calloc(n, sizeof(float));
+        }
+    }
+    return OR_OK;
+}
+
+static void hier_free(or_hier* H)
+{
+    for (int l = 0; l < H->nlev; ++l) {
+        free(H->r[l]);
+        if (l > 0) { free(H->phi[l]); free(H->b[l]); }
+        free(H->phif[l]); free(H->bf[l]); free(H->rf[l]);
+    }
+}
+
+/* Coarsest-level solve: CG for the correction e of the current iterate, i.e.
+ * A e = b - A phi from e = 0, then phi += e.  On coarse levels phi is zero on
+ * entry, so this is CG on A phi = b. */
+static void coarse_solve_d(or_hier* H, int l)
+{
+    const or_level* L = &H->lev[l];
+    const size_t n = or_cells(L);
+    double* e = (double*)calloc(n, sizeof(double));
+    residual_d(L, H->phi[l], H->b[l], H->r[l]);
+    H->cg_iters_last = cg_d(L, H->r[l], e, H->cg_rtol, H->cg_maxit);
+    for (size_t c = 0; c < n; ++c) H->phi[l][c] += e[c];
+    free(e);
+}
+
+/* V(nu1,nu2)-cycle on level l (Sec. 3): pre-smooth, restrict the residual,
+ * recurse from a zero coarse guess, prolongate with the magnified correction,
+ * post-smooth.  The coarsest level is solved by CG. */
+static void vcycle_d(or_hier* H, int l)
+{
+    const or_level* L = &H->lev[l];
+    if (l == H->nlev - 1) { coarse_solve_d(H, l); return; }
+    for (int s = 0; s < H->nu1; ++s) rbgs_sweep_d(L, H->phi[l], H->b[l]);
+    residual_d(L, H->phi[l], H->b[l], H->r[l]);
+    restrict_avg_d(L, H->r[l], H->b[l + 1]);
+    memset(H->phi[l + 1], 0, or_cells(&H->lev[l + 1]) * sizeof(double));
+    vcycle_d(H, l + 1);
+    prolong_add_d(L, H->phi[l + 1], H->omega, H->phi[l]);
+    for (int s = 0; s < H->nu2; ++s) rbgs_sweep_d(L, H->phi[l], H->b[l]);
+}
+
+/* FP32 cycle: the same steps in float arithmetic; the coarsest level is still
+ * solved by FP64 CG on the float right-hand side. */
+static void vcycle_f(or_hier* H, int l)
+{
+    const or_level* L = &H->lev[l];
+    const size_t n = or_cells(L);
+    if (l == H->nlev - 1) {
+        double* bd = (double*)malloc(n * sizeof(double));
+        double* x = (double*)malloc(n * sizeof(double));
+        /* correction of the current float iterate, computed in FP64 */
+        for (size_t c = 0; c < n; ++c) bd[c] = (double)H->bf[l][c];
+        double* pd = (double*)malloc(n * sizeof(double));
+        for (size_t c = 0; c < n; ++c) pd[c] = (double)H->phif[l][c];
+        residual_d(L, pd, bd, H->r[l]);
+        H->cg_iters_last = cg_d(L, H->r[l], x, H->cg_rtol, H->cg_maxit);
+        for (size_t c = 0; c < n; ++c) H->phif[l][c] = (float)(pd[c] + x[c]);
+        free(bd); free(x); free(pd);
+        return;
+    }
+    for (int s = 0; s < H->nu1; ++s) rbgs_sweep_f(L, H->phif[l], H->bf[l]);
+    residual_f(L, H->phif[l], H->bf[l], H->rf[l]);
+    restrict_avg_f(L, H->rf[l], H->bf[l + 1]);
+    memset(H->phif[l + 1], 0, or_cells(&H->lev[l + 1]) * sizeof(float));
+    vcycle_f(H, l + 1);
+    prolong_add_f(L, H->phif[l + 1], (float)H->omega, H->phif[l]);
+    for (int s = 0; s < H->nu2; ++s) rbgs_sweep_f(L, H->phif[l], H->bf[l]);
+}
+
+/* ============================ exported API ==================================== */
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int or_diag_at(int nx, int ny, int nz, const int* kinds, int i, int j, int k)
+{
+    or_level L = make_level(nx, ny, nz, 1.0, 0, kinds);
+    return or_diag(&L, i, j, k);
+}
+
+void or_apply(int nx, int ny, int nz, double h, int level, const int* kinds,
+              const double* phi, double* out)
+{
+    or_level L = make_level(nx, ny, nz, h, level, kinds);
+    apply_d(&L, phi, out);
+}
+
+void or_residual(int nx, int ny, int nz, double h, int level, const int* kinds,
+                 const double* phi, const double* b, double* r)
+{
+    or_level L = make_level(nx, ny, nz, h, level, kinds);
+    residual_d(&L, phi, b, r);
+}
+
+double or_norm2(long long n, const double* v) { return norm2_d((size_t)n, v); }
+
+void or_rbgs_sweep(int nx, int ny, int nz, double h, int level, const int* kinds,
+                   double* phi, const double* b)
+{
+    or_level L = make_level(nx, ny, nz, h, level, kinds);
+    rbgs_sweep_d(&L, phi, b);
+}
+
+void or_restrict(int nx, int ny, int nz, const double* r, double* bc)
+{
+    static const int k0[6] = {0, 0, 0, 0, 0, 0};
+    or_level L = make_level(nx, ny, nz, 1.0, 0, k0);
+    restrict_avg_d(&L, r, bc);
+}
+
+void or_prolong_add(int nx, int ny, int nz, const double* ec, double omega, double* phi)
+{
+    static const int k0[6] = {0, 0, 0, 0, 0, 0};
+    or_level L = make_level(nx, ny, nz, 1.0, 0, k0);
+    prolong_add_d(&L, ec, omega, phi);
+}
+
+int or_cg(int nx, int ny, int nz, double h, int level, const int* kinds,
+          const double* b, double* x, double rtol, int maxit)
+{
+    or_level L = make_level(nx, ny, nz, h, level, kinds);
+    return cg_d(&L, b, x, rtol, maxit);
+}
+
+/* RHS adaptation to the boundary conditions on the finest level (Sec. 2.4 and
+ * Sec. 5.3): b = f plus, for every boundary face a cell touches, 2 g_d / h^2
+ * (Dirichlet, value on the face) or g_n / h (Neumann, outward derivative). */
+void or_fold(int nx, int ny, int nz, double h, const int* kinds, const double* values,
+             const double* f, double* b)
+{
+    or_level L = make_level(nx, ny, nz, h, 0, kinds);
+    double term[6];
+    for (int fc = 0; fc < 6; ++fc)
+        term[fc] = kinds[fc] == OR_DIRICHLET ? 2.0 * values[fc] / (h * h) : values[fc] / h;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t c = IDX(&L, i, j, k);
+                double v = f[c];
+                if (i == 0)      v += term[0];
+                if (i == nx - 1) v += term[1];
+                if (j == 0)      v += term[2];
+                if (j == ny - 1) v += term[3];
+                if (k == 0)      v += term[4];
+                if (k == nz - 1) v += term[5];
+                b[c] = v;
+            }
+}
+
+/* Is the centre of cell (i,j,k) inside the closed ball (c, R)?  Evaluated as
+ * dx*dx + dy*dy + dz*dz <= R*R, left to right, no contraction. */
+static int inside_ball(int i, int j, int k, double h, const double* c, double R)
+{
+    const double dx = ((double)i + 0.5) * h - c[0];
+    const double dy = ((double)j + 0.5) * h - c[1];
+    const double dz = ((double)k + 0.5) * h - c[2];
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    return d2 <= R * R;
+}
+
+/* candidate index range of one axis: every cell whose centre can be within R
+ * of c, widened by one cell, clipped to the grid */
+static void axis_range(double c, double R, double h, int n, int* lo, int* hi)
+{
+    int a = (int)floor((c - R) / h - 0.5) - 1;
+    int b = (int)ceil((c + R) / h - 0.5) + 1;
+    *lo = a < 0 ? 0 : a;
+    *hi = b > n - 1 ? n - 1 : b;
+}
+
+static long long sphere_count(int nx, int ny, int nz, double h, const double* c, double R)
+{
+    int ilo, ihi, jlo, jhi, klo, khi;
+    axis_range(c[0], R, h, nx, &ilo, &ihi);
+    axis_range(c[1], R, h, ny, &jlo, &jhi);
+    axis_range(c[2], R, h, nz, &klo, &khi);
+    long long cnt = 0;
+    for (int k = klo; k <= khi; ++k)
+        for (int j = jlo; j <= jhi; ++j)
+            for (int i = ilo; i <= ihi; ++i)
+                cnt += inside_ball(i, j, k, h, c, R);
+    return cnt;
+}
+
+/* Charge deposition (Sec. 2.4, naive volume mapping with the charge spread
+ * evenly over the covered cells): f = rho/eps, f_c = sum over spheres s that
+ * cover cell c of q_s / (eps n_s h^3).  Spheres are added in index order.
+ * counts[s] receives n_s (may be NULL).  A sphere that covers no cell centre
+ * deposits nothing. */
+void or_deposit(int nx, int ny, int nz, double h, int n, const double* centers,
+                const double* radii, const double* q, double eps, double* f, long long* counts)
+{
+    const or_level L = make_level(nx, ny, nz, h, 0, (const int[6]){0, 0, 0, 0, 0, 0});
+    memset(f, 0, or_cells(&L) * sizeof(double));
+    for (int s = 0; s < n; ++s) {
+        const double* c = centers + 3 * (size_t)s;
+        const double R = radii[s];
+        const long long ns = sphere_count(nx, ny, nz, h, c, R);
+        if (counts) counts[s] = ns;
+        if (ns == 0) continue;
+        const double val = q[s] / (eps * (double)ns * h * h * h);
+        int ilo, ihi, jlo, jhi, klo, khi;
+        axis_range(c[0], R, h, nx, &ilo, &ihi);
+        axis_range(c[1], R, h, ny, &jlo, &jhi);
+        axis_range(c[2], R, h, nz, &klo, &khi);
+        for (int k = klo; k <= khi; ++k)
+            for (int j = jlo; j <= jhi; ++j)
+                for (int i = ilo; i <= ihi; ++i)
+                    if (inside_ball(i, j, k, h, c, R)) f[IDX(&L, i, j, k)] += val;
+    }
+}
+
+/* Gradient of a loss with respect to the sphere charges, given the adjoint
+ * lambda = dL/df:  dL/dq_s = sum over covered cells of lambda_c / (eps n_s h^3). */
+void or_dq(int nx, int ny, int nz, double h, int n, const double* centers, const double* radii,
+           double eps, const double* lambda, double* dq)
+{
+    const or_level L = make_level(nx, ny, nz, h, 0, (const int[6]){0, 0, 0, 0, 0, 0});
+    for (int s = 0; s < n; ++s) {
+        const double* c = centers + 3 * (size_t)s;
+        const double R = radii[s];
+        const long long ns = sphere_count(nx, ny, nz, h, c, R);
+        if (ns == 0) { dq[s] = 0.0; continue; }
+        int ilo, ihi, jlo, jhi, klo, khi;
+        axis_range(c[0], R, h, nx, &ilo, &ihi);
+        axis_range(c[1], R, h, ny, &jlo, &jhi);
+        axis_range(c[2], R, h, nz, &klo, &khi);
+        double acc = 0.0;
+        for (int k = klo; k <= khi; ++k)
+            for (int j = jlo; j <= jhi; ++j)
+                for (int i = ilo; i <= ihi; ++i)
+                    if (inside_ball(i, j, k, h, c, R)) acc += lambda[IDX(&L, i, j, k)];
+        dq[s] = acc / (eps * (double)ns * h * h * h);
+    }
+}
+
+/* Multigrid solve (Alg. 1): with rho_k = ||b - A phi_k||_2 / ||b||_2, perform
+ * V-cycles while rho_k >= rtol, at most max_cycles.  b is the folded finest
+ * right-hand side; phi holds the initial guess on entry.  hist[0..cycles]
+ * receives rho_0..rho_cycles.  If ||b|| = 0, phi is set to 0 and no cycle is
+ * run.  Returns OR_OK, OR_E_NOCONV or OR_E_NONFINITE. */
+int or_solve(int nx, int ny, int nz, double h, const int* kinds, int levels, int nu1, int nu2,
+             double omega, double cg_rtol, int cg_maxit, const double* b, double* phi,
+             double rtol, int max_cycles, double* hist, int* cycles_out)
+{
+    or_hier H;
+    if (hier_init(&H, nx, ny, nz, h, kinds, levels, nu1, nu2, omega, cg_rtol, cg_maxit, 0))
+        return OR_E_ARG;
+    const or_level* L0 = &H.lev[0];
+    const size_t n = or_cells(L0);
+    H.phi[0] = phi;
+    H.b[0] = (double*)b;
+    const double bnorm = norm2_d(n, b);
+    int k = 0, status = OR_OK;
+    if (bnorm == 0.0) {
+        memset(phi, 0, n * sizeof(double));
+        if (hist) hist[0] = 0.0;
+    } else {
+        residual_d(L0, phi, b, H.r[0]);
+        double rho = norm2_d(n, H.r[0]) / bnorm;
+        if (hist) hist[0] = rho;
+        while (isfinite(rho) && rho >= rtol && k < max_cycles) {
+            vcycle_d(&H, 0);
+            ++k;
+            residual_d(L0, phi, b, H.r[0]);
+            rho = norm2_d(n, H.r[0]) / bnorm;
+            if (hist) hist[k] = rho;
+        }
+        if (!isfinite(rho)) status = OR_E_NONFINITE;
+        else if (rho >= rtol) status = OR_E_NOCONV;
+    }
+    if (cycles_out) *cycles_out = k;
+    H.phi[0] = NULL; H.b[0] = NULL;
+    hier_free(&H);
+    return status;
+}
+
+/* Power of two nearest below |x| (x > 0): scaling by it is exact. */
+static double pow2_floor(double x)
+{
+    int e;
+    frexp(x, &e);
+    return ldexp(1.0, e - 1);
+}
+
+/* FP32-in-FP64 iterative refinement.  The outer loop is FP64: residual
+ * r = b - A phi, its norm, and the update.  Each outer step scales r by a
+ * power of two sigma (the one just below ||r||), rounds it to float, runs
+ * `inner` FP32 V-cycles on A c = r/sigma from c = 0 (coarsest level in FP64),
+ * and adds sigma * c to phi.  Stops when ||b - A phi|| / ||b|| < rtol or after
+ * max_outer steps.  hist[0..outer] receives the relative residuals. */
+int or_solve_ir(int nx, int ny, int nz, double h, const int* kinds, int levels, int nu1, int nu2,
+                double omega, double cg_rtol, int cg_maxit, int inner, const double* b, double* phi,
+                double rtol, int max_outer, double* hist, int* outer_out)
+{
+    or_hier H;
+    if (hier_init(&H, nx, ny, nz, h, kinds, levels, nu1, nu2, omega, cg_rtol, cg_maxit, 1))
+        return OR_E_ARG;
+    const or_level* L0 = &H.lev[0];
+    const size_t n = or_cells(L0);
+    const double bnorm = norm2_d(n, b);
+    int k = 0, status = OR_OK;
+    if (bnorm == 0.0) {
+        memset(phi, 0, n * sizeof(double));
+        if (hist) hist[0] = 0.0;
+    } else {
+        double* r = H.r[0];
+        residual_d(L0, phi, b, r);
+        double rnorm = norm2_d(n, r);
+        double rho = rnorm / bnorm;
+        if (hist) hist[0] = rho;
+        while (isfinite(rho) && rho >= rtol && k < max_outer) {
+            const double sigma = pow2_floor(rnorm);
+            for (size_t c = 0; c < n; ++c) H.bf[0][c] = (float)(r[c] / sigma);
+            memset(H.phif[0], 0, n * sizeof(float));
+            for (int m = 0; m < inner; ++m) vcycle_f(&H, 0);
+            for (size_t c = 0; c < n; ++c) phi[c] += sigma * (double)H.phif[0][c];
+            ++k;
+            residual_d(L0, phi, b, r);
+            rnorm = norm2_d(n, r);
+            rho = rnorm / bnorm;
+            if (hist) hist[k] = rho;
+        }
+        if (!isfinite(rho)) status = OR_E_NONFINITE;
+        else if (rho >= rtol) status = OR_E_NOCONV;
+    }
+    if (outer_out) *outer_out = k;
+    hier_free(&H);
+    return status;
+}
