@@ -1,0 +1,179 @@
+/*
+ * ccmg.h -- C ABI of the cell-centered geometric multigrid Poisson solver for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The solver computes the electric potential phi of
+ *     -Lap(phi) = rho / eps                 (Sec. 2.4, Eq. Poisson)
+ * on a uniform cell grid with the finite-volume 7-point stencil and
+ * per-face Dirichlet or Neumann conditions folded into stencil and right-hand
+ * side (Sec. 2.4, "Boundary conditions"; Sec. 5.3), by the cell-centered
+ * multigrid of Sec. 3 / Sec. 5.3 (2x2x2 coarsening, averaging restriction,
+ * nearest-neighbour prolongation with the correction magnified by omega,
+ * Galerkin coarse operators, red-black Gauss-Seidel smoothing, CG on the
+ * coarsest grid, V-cycles until the residual L2 norm drops below a tolerance,
+ * Alg. 1), of D. Bartuschat and U. Ruede, "Parallel Multiphysics Simulations
+ * of Charged Particles in Microfluidic Flows", arXiv:1410.6609.
+ * Two extensions: FP32 V-cycles inside FP64 iterative refinement, and the
+ * adjoint solve giving gradients with respect to the charges.
+ *
+ * Conventions for every entry point:
+ *  - Arrays are contiguous [nz][ny][nx] (x fastest).  Cell (i,j,k) has its
+ *    centre at ((i+1/2)h, (j+1/2)h, (k+1/2)h).
+ *  - Pointers named d_* must be device memory of the current HIP device; the
+ *    caller owns them.  The library never allocates device memory: its
+ *    scratch space is a caller-owned workspace (ccmg_set_workspace).
+ *  - Work is enqueued on the HIP stream given to ccmg_create (0 = the null
+ *    stream).  Calls that return norms or statistics synchronise that stream;
+ *    all others return without waiting.
+ *  - Return value: CCMG_OK (0) or a negative CCMG_E_* code; then
+ *    ccmg_last_error() holds a message.  No C++ exception crosses the ABI.
+ *  - One solver object must not be used by two threads at once.
+ */
+#ifndef CCMG_H
+#define CCMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ccmg_solver ccmg_solver;
+
+/* face kinds; faces are numbered 0..5 = x-, x+, y-, y+, z-, z+ */
+enum { CCMG_DIRICHLET = 0, CCMG_NEUMANN = 1 };
+
+/* precision modes */
+enum { CCMG_FP64 = 0, CCMG_FP32_IR = 1 };
+
+/* status codes */
+enum {
+    CCMG_OK = 0,
+    CCMG_E_ARG = -1,       /* bad argument (null, host pointer, out of range) */
+    CCMG_E_DIMS = -2,      /* dims not divisible by 2^(levels-1), or coarsest grid too large */
+    CCMG_E_SINGULAR = -3,  /* no Dirichlet face: the operator is singular */
+    CCMG_E_HIP = -4,       /* a HIP runtime call failed */
+    CCMG_E_NONFINITE = -5, /* the residual became NaN or Inf */
+    CCMG_E_NOCONV = -6,    /* max_cycles reached before the tolerance (phi holds the last iterate) */
+    CCMG_E_STATE = -7      /* no (or too small) workspace attached */
+};
+
+#define CCMG_MAX_LEVELS 16
+#define CCMG_MAX_CYCLES 1000
+#define CCMG_MAX_COARSE_CELLS 4096
+
+/* One boundary face.  Dirichlet: value = phi on the face (half a cell outside
+ * the last cell centre).  Neumann: value = outward normal derivative dphi/dn. */
+typedef struct {
+    int kind;
+    double value;
+} ccmg_face;
+
+typedef struct {
+    int nu1, nu2;         /* pre- and post-smoothing RB-GS sweeps (default 2, 2; Sec. 3: V(1,1) is unreliable) */
+    int levels;           /* hierarchy depth; 0 = coarsen while the dims stay even and the grid exceeds 512 cells */
+    double omega;         /* coarse-correction factor (default 2.0; Sec. 3 "about 2") */
+    int precision;        /* CCMG_FP64 or CCMG_FP32_IR */
+    int ir_inner_cycles;  /* FP32 V-cycles per refinement step (default 2) */
+    double cg_rtol;       /* coarsest-grid CG: stop at ||r|| <= cg_rtol ||b|| (default 1e-13) */
+    int cg_maxit;         /* coarsest-grid CG iteration cap (0 = 2 x coarsest cells) */
+    int fuse_sweeps;      /* RB-GS sweeps fused per smoother kernel pass: 1 or 2 (default 2); iterates are identical */
+} ccmg_options;
+
+typedef struct {
+    int cycles;           /* V-cycles (FP64) or refinement steps (FP32-IR) performed */
+    int inner_cycles;     /* FP32 V-cycles performed (FP32-IR), else equal to cycles */
+    double rel_res0;      /* ||b - A phi_0|| / ||b|| of the initial guess */
+    double rel_res;       /* ||b - A phi|| / ||b|| on return */
+    double seconds;       /* host wall time of the call, including the final synchronisation */
+} ccmg_stats;
+
+/* Fill *opt with the defaults listed above. */
+void ccmg_default_options(ccmg_options* opt);
+
+/* Create a solver for an nx x ny x nz cell grid of spacing h > 0 with the six
+ * face conditions bc[0..5] (x-, x+, y-, y+, z-, z+).  opt may be NULL for the
+ * defaults.  hip_stream is a hipStream_t (NULL = null stream).  Builds the
+ * level hierarchy on the host (Sec. 3: a level is coarsened by 2x2x2 while the
+ * cell counts per dimension stay even); touches no device memory.
+ * Errors: E_ARG (null out/bc, h <= 0, bad kinds or options), E_DIMS (a dim not
+ * divisible by 2^(levels-1), coarsest grid over CCMG_MAX_COARSE_CELLS cells),
+ * E_SINGULAR (all six faces Neumann). */
+int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_face bc[6],
+                const ccmg_options* opt, void* hip_stream);
+
+/* Bytes of device workspace the solver needs (hierarchy arrays, ping-pong
+ * buffers, norm partials and the control block). */
+size_t ccmg_workspace_bytes(const ccmg_solver* s);
+
+/* Attach caller-owned device memory of at least ccmg_workspace_bytes() bytes,
+ * 256-byte aligned.  It must stay valid while the solver is used.
+ * Errors: E_ARG (null, host memory, misaligned), E_STATE (too small). */
+int ccmg_set_workspace(ccmg_solver* s, void* d_ptr, size_t bytes);
+
+/* Enqueue later calls on another stream. */
+int ccmg_set_stream(ccmg_solver* s, void* hip_stream);
+
+/* Number of levels and the cell counts of level l (l = 0 finest). */
+int ccmg_num_levels(const ccmg_solver* s);
+int ccmg_level_dims(const ccmg_solver* s, int l, int dims_out[3]);
+
+/* Charge deposition (Sec. 2.4, naive volume mapping): for each sphere s with
+ * centre d_centers[3s..3s+2], radius d_radii[s] (physical units) and charge
+ * d_q[s], the cells whose centre lies in the closed ball are its n_s cells,
+ * and every one of them receives q_s / (eps n_s h^3) in d_f = rho / eps, which
+ * is overwritten.  Overlapping spheres add (in unspecified order).  A sphere
+ * covering no cell centre deposits nothing.  d_counts (nullable, int[n])
+ * receives n_s.  n = 0 just zeroes d_f. */
+int ccmg_deposit_charges(ccmg_solver* s, int n, const double* d_centers, const double* d_radii,
+                         const double* d_q, double eps, double* d_f, int* d_counts);
+
+/* One V(nu1,nu2)-cycle on d_phi (in/out) for the right-hand side d_f (= rho/eps,
+ * boundary values taken from the faces).  rel_res_out (nullable): the relative
+ * residual ||b - A phi|| / ||b|| after the cycle (synchronises). */
+int ccmg_vcycle(ccmg_solver* s, double* d_phi, const double* d_f, double* rel_res_out);
+
+/* Multigrid solve (Alg. 1): d_phi holds the initial guess on entry (it is not
+ * zeroed) and the solution on return.  Cycles (FP64) or refinement steps
+ * (FP32-IR) are performed while ||b - A phi|| / ||b|| >= rtol, at most
+ * max_cycles (<= CCMG_MAX_CYCLES).  If ||b|| = 0, phi is set to 0.
+ * st (nullable) receives the statistics.  Returns E_NOCONV if the tolerance
+ * was not reached (phi holds the last iterate), E_NONFINITE on NaN/Inf. */
+int ccmg_solve(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles,
+               ccmg_stats* st);
+
+/* Adjoint solve for a loss L(phi): given d_g = dL/dphi, solves A lambda = g
+ * with the same operator and homogeneous boundary values (A is symmetric), from
+ * lambda = 0, into d_lambda = dL/df.  With n > 0 spheres (same arrays as the
+ * deposition) d_dq (nullable, double[n]) receives dL/dq_s = sum over the
+ * sphere's cells of lambda_c / (eps n_s h^3); d_drho (nullable) receives
+ * dL/drho = lambda / eps.  Stopping rule, statistics and errors as ccmg_solve. */
+int ccmg_adjoint_solve(ccmg_solver* s, const double* d_g, double* d_lambda, int n,
+                       const double* d_centers, const double* d_radii, double eps, double* d_dq,
+                       double* d_drho, double rtol, int max_cycles, ccmg_stats* st);
+
+/* Residual of the finest level: d_r (nullable) = b - A phi with b the folded
+ * right-hand side of d_f; rel_res_out (nullable) = ||b - A phi|| / ||b||. */
+int ccmg_residual(ccmg_solver* s, const double* d_phi, const double* d_f, double* d_r,
+                  double* rel_res_out);
+
+/* The smoother alone: `sweeps` red-black Gauss-Seidel sweeps on the finest
+ * level for the folded right-hand side of d_f, in place on d_phi (the same
+ * smoother kernels the cycle runs; for tests and bandwidth measurement). */
+int ccmg_smooth(ccmg_solver* s, double* d_phi, const double* d_f, int sweeps);
+
+/* Relative residuals rho_0..rho_k of the last solve (k = cycles); copies at
+ * most `max` values into host memory and returns how many it copied. */
+int ccmg_history(const ccmg_solver* s, double* out, int max);
+
+/* Message of the last error on this solver ("" if none); s may be NULL for
+ * errors of ccmg_create. */
+const char* ccmg_last_error(const ccmg_solver* s);
+
+void ccmg_destroy(ccmg_solver* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCMG_H */

@@ -1,0 +1,334 @@
+"""MI355X cell-centered multigrid solver for the electric-potential Poisson problem.
+
+Thin Python binding of ``libccmg.so`` (C ABI in ``include/ccmg.h``).  Every
+step of the method runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch supplies device memory (tensors, the workspace)
+and the stream.  The method is the cell-centered multigrid of Bartuschat &
+Ruede, "Parallel Multiphysics Simulations of Charged Particles in
+Microfluidic Flows" (arXiv:1410.6609), Sec. 2.4, Sec. 3 and Sec. 5.3.
+
+There is no CPU fallback: if the library is missing, importing a solver
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+__all__ = [
+    "DIRICHLET", "NEUMANN", "FP64", "FP32_IR", "CcmgError", "Options", "Stats", "Solver",
+    "PoissonFn", "RhsSolveFn", "lib", "LIB_PATH", "exported_symbols",
+]
+
+DIRICHLET, NEUMANN = 0, 1
+FP64, FP32_IR = 0, 1
+OK, E_ARG, E_DIMS, E_SINGULAR, E_HIP, E_NONFINITE, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+_ERR_NAMES = {E_ARG: "E_ARG", E_DIMS: "E_DIMS", E_SINGULAR: "E_SINGULAR", E_HIP: "E_HIP",
+              E_NONFINITE: "E_NONFINITE", E_NOCONV: "E_NOCONV", E_STATE: "E_STATE"}
+MAX_CYCLES = 1000
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libccmg.so")
+
+
+class CcmgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Face(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("value", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("levels", ctypes.c_int),
+                ("omega", ctypes.c_double), ("precision", ctypes.c_int),
+                ("ir_inner_cycles", ctypes.c_int), ("cg_rtol", ctypes.c_double),
+                ("cg_maxit", ctypes.c_int), ("fuse_sweeps", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("inner_cycles", ctypes.c_int),
+                ("rel_res0", ctypes.c_double), ("rel_res", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+@dataclass
+class Options:
+    nu1: int = 2
+    nu2: int = 2
+    levels: int = 0
+    omega: float = 2.0
+    precision: int = FP64
+    ir_inner_cycles: int = 2
+    cg_rtol: float = 1e-13
+    cg_maxit: int = 0
+    fuse_sweeps: int = 2
+
+    def _c(self) -> _Options:
+        return _Options(self.nu1, self.nu2, self.levels, self.omega, self.precision,
+                        self.ir_inner_cycles, self.cg_rtol, self.cg_maxit, self.fuse_sweeps)
+
+
+@dataclass
+class Stats:
+    cycles: int
+    inner_cycles: int
+    rel_res0: float
+    rel_res: float
+    seconds: float
+    status: int = 0
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_SIGS = {
+    "ccmg_default_options": ([ctypes.POINTER(_Options)], None),
+    "ccmg_create": ([ctypes.POINTER(_VP), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                     ctypes.POINTER(_Face), ctypes.POINTER(_Options), _VP], ctypes.c_int),
+    "ccmg_workspace_bytes": ([_VP], ctypes.c_size_t),
+    "ccmg_set_workspace": ([_VP, _VP, ctypes.c_size_t], ctypes.c_int),
+    "ccmg_set_stream": ([_VP, _VP], ctypes.c_int),
+    "ccmg_num_levels": ([_VP], ctypes.c_int),
+    "ccmg_level_dims": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "ccmg_deposit_charges": ([_VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_double, _VP, _VP], ctypes.c_int),
+    "ccmg_vcycle": ([_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "ccmg_solve": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
+    "ccmg_adjoint_solve": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_double, _VP, _VP,
+                            ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
+    "ccmg_residual": ([_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "ccmg_smooth": ([_VP, _VP, _VP, ctypes.c_int], ctypes.c_int),
+    "ccmg_history": ([_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
+    "ccmg_last_error": ([_VP], ctypes.c_char_p),
+    "ccmg_destroy": ([_VP], None),
+}
+
+
+def exported_symbols() -> Sequence[str]:
+    return tuple(_SIGS)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libccmg.so (built by paper_1410_6609_amd/build.py); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1410_6609_amd/build.py`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Solver:
+    """One solver context: grid, faces, options, workspace (a torch tensor).
+
+    shape = (nx, ny, nz); fields are tensors of shape (nz, ny, nx), float64, on
+    the solver's device.  faces: 6 pairs (kind, value) for x-, x+, y-, y+, z-, z+.
+    """
+
+    def __init__(self, shape: Tuple[int, int, int], h: float, faces: Sequence[Tuple[int, float]],
+                 options: Optional[Options] = None, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the solver runs on a GPU device only")
+        self.shape = tuple(int(n) for n in shape)
+        self.h = float(h)
+        self.faces = [(int(k), float(v)) for k, v in faces]
+        if len(self.faces) != 6:
+            raise ValueError("six faces required")
+        self.options = options or Options()
+        L = lib()
+        arr = (_Face * 6)(*[_Face(k, v) for k, v in self.faces])
+        opt = self.options._c()
+        handle = ctypes.c_void_p()
+        nx, ny, nz = self.shape
+        with torch.cuda.device(self.device):
+            rc = L.ccmg_create(ctypes.byref(handle), nx, ny, nz, self.h, arr, ctypes.byref(opt),
+                               _stream_handle(self.device))
+        if rc != OK:
+            raise CcmgError(rc, L.ccmg_last_error(None).decode())
+        self._h = handle
+        nbytes = L.ccmg_workspace_bytes(handle)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self._check(L.ccmg_set_workspace(handle, ctypes.c_void_p(aligned), nbytes))
+
+    # -- plumbing -------------------------------------------------------------
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.ccmg_destroy(h)
+            self._h = None
+
+    def _check(self, rc: int, allow=()):
+        if rc != OK and rc not in allow:
+            raise CcmgError(rc, lib().ccmg_last_error(self._h).decode())
+        return rc
+
+    def _bind_stream(self):
+        lib().ccmg_set_stream(self._h, _stream_handle(self.device))
+
+    def _field(self, t: torch.Tensor, name: str) -> torch.Tensor:
+        nx, ny, nz = self.shape
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a tensor")
+        if t.device != self.device or t.dtype != torch.float64 or tuple(t.shape) != (nz, ny, nx):
+            raise ValueError(f"{name} must be float64 of shape {(nz, ny, nx)} on {self.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def _spheres(self, centers, radii):
+        centers = centers.to(self.device, torch.float64).contiguous().reshape(-1, 3)
+        radii = radii.to(self.device, torch.float64).contiguous().reshape(-1)
+        if centers.shape[0] != radii.shape[0]:
+            raise ValueError("centers and radii disagree in length")
+        return centers, radii
+
+    @property
+    def levels(self) -> int:
+        return lib().ccmg_num_levels(self._h)
+
+    def level_dims(self, l: int) -> Tuple[int, int, int]:
+        d = (ctypes.c_int * 3)()
+        self._check(lib().ccmg_level_dims(self._h, l, d))
+        return tuple(d)
+
+    def zeros(self) -> torch.Tensor:
+        nx, ny, nz = self.shape
+        return torch.zeros((nz, ny, nx), dtype=torch.float64, device=self.device)
+
+    # -- the method -----------------------------------------------------------
+    def deposit(self, centers, radii, q, eps: float = 1.0, out: Optional[torch.Tensor] = None,
+                counts: bool = False):
+        """f = rho / eps from charged spheres (naive volume mapping)."""
+        centers, radii = self._spheres(centers, radii)
+        q = q.to(self.device, torch.float64).contiguous().reshape(-1)
+        n = radii.shape[0]
+        f = self.zeros() if out is None else self._field(out, "out")
+        cnt = torch.zeros(n, dtype=torch.int32, device=self.device) if counts else None
+        self._bind_stream()
+        self._check(lib().ccmg_deposit_charges(self._h, n, _ptr(centers), _ptr(radii), _ptr(q), float(eps),
+                                               _ptr(f), _ptr(cnt)))
+        return (f, cnt) if counts else f
+
+    def solve(self, f: torch.Tensor, phi: Optional[torch.Tensor] = None, rtol: float = 1e-10,
+              max_cycles: int = 100, check: bool = True):
+        """Solve A phi = b(f) in place on phi (zeros if None).  Returns (phi, Stats)."""
+        f = self._field(f, "f")
+        phi = self.zeros() if phi is None else self._field(phi, "phi")
+        st = _Stats()
+        self._bind_stream()
+        rc = lib().ccmg_solve(self._h, _ptr(phi), _ptr(f), float(rtol), int(max_cycles), ctypes.byref(st))
+        if check:
+            self._check(rc)
+        s = Stats(st.cycles, st.inner_cycles, st.rel_res0, st.rel_res, st.seconds, rc)
+        return phi, s
+
+    def vcycle(self, phi: torch.Tensor, f: torch.Tensor, norm: bool = True) -> Optional[float]:
+        f = self._field(f, "f")
+        phi = self._field(phi, "phi")
+        out = ctypes.c_double(0.0)
+        self._bind_stream()
+        self._check(lib().ccmg_vcycle(self._h, _ptr(phi), _ptr(f), ctypes.byref(out) if norm else None))
+        return out.value if norm else None
+
+    def adjoint(self, g: torch.Tensor, centers=None, radii=None, eps: float = 1.0, rtol: float = 1e-10,
+                max_cycles: int = 100, want_drho: bool = False, lam: Optional[torch.Tensor] = None,
+                check: bool = True):
+        """lambda = A^{-1} g; optional dL/dq per sphere and dL/drho.  Returns (lam, dq, drho, Stats)."""
+        g = self._field(g, "g")
+        lam = self.zeros() if lam is None else self._field(lam, "lam")
+        n = 0
+        dq = None
+        c = r = None
+        if centers is not None:
+            c, r = self._spheres(centers, radii)
+            n = r.shape[0]
+            dq = torch.zeros(n, dtype=torch.float64, device=self.device)
+        drho = self.zeros() if want_drho else None
+        st = _Stats()
+        self._bind_stream()
+        rc = lib().ccmg_adjoint_solve(self._h, _ptr(g), _ptr(lam), n, _ptr(c), _ptr(r), float(eps), _ptr(dq),
+                                      _ptr(drho), float(rtol), int(max_cycles), ctypes.byref(st))
+        if check:
+            self._check(rc)
+        return lam, dq, drho, Stats(st.cycles, st.inner_cycles, st.rel_res0, st.rel_res, st.seconds, rc)
+
+    def residual(self, phi: torch.Tensor, f: torch.Tensor, want_field: bool = True):
+        phi = self._field(phi, "phi")
+        f = self._field(f, "f")
+        r = self.zeros() if want_field else None
+        out = ctypes.c_double(0.0)
+        self._bind_stream()
+        self._check(lib().ccmg_residual(self._h, _ptr(phi), _ptr(f), _ptr(r), ctypes.byref(out)))
+        return r, out.value
+
+    def smooth(self, phi: torch.Tensor, f: torch.Tensor, sweeps: int = 1) -> torch.Tensor:
+        phi = self._field(phi, "phi")
+        f = self._field(f, "f")
+        self._bind_stream()
+        self._check(lib().ccmg_smooth(self._h, _ptr(phi), _ptr(f), int(sweeps)))
+        return phi
+
+    def history(self):
+        buf = (ctypes.c_double * (MAX_CYCLES + 1))()
+        n = lib().ccmg_history(self._h, buf, MAX_CYCLES + 1)
+        return list(buf[:n])
+
+
+class PoissonFn(torch.autograd.Function):
+    """phi = A^{-1} b(deposit(q)) for charged spheres; backward gives dL/dq by the
+    adjoint multigrid solve of the same symmetric operator."""
+
+    @staticmethod
+    def forward(ctx, q, centers, radii, solver: Solver, eps: float = 1.0, rtol: float = 1e-10,
+                max_cycles: int = 100):
+        f = solver.deposit(centers, radii, q, eps)
+        phi, st = solver.solve(f, rtol=rtol, max_cycles=max_cycles)
+        ctx.solver, ctx.eps, ctx.rtol, ctx.max_cycles = solver, eps, rtol, max_cycles
+        ctx.save_for_backward(centers, radii)
+        ctx.stats = st
+        return phi
+
+    @staticmethod
+    def backward(ctx, grad_phi):
+        centers, radii = ctx.saved_tensors
+        g = grad_phi.contiguous().to(torch.float64)
+        _, dq, _, _ = ctx.solver.adjoint(g, centers, radii, ctx.eps, ctx.rtol, ctx.max_cycles)
+        return dq, None, None, None, None, None, None
+
+
+class RhsSolveFn(torch.autograd.Function):
+    """phi = A^{-1} b(f) for a right-hand side f = rho / eps; backward gives
+    dL/df = lambda."""
+
+    @staticmethod
+    def forward(ctx, f, solver: Solver, rtol: float = 1e-10, max_cycles: int = 100):
+        phi, _ = solver.solve(f.contiguous(), rtol=rtol, max_cycles=max_cycles)
+        ctx.solver, ctx.rtol, ctx.max_cycles = solver, rtol, max_cycles
+        return phi
+
+    @staticmethod
+    def backward(ctx, grad_phi):
+        lam, _, _, _ = ctx.solver.adjoint(grad_phi.contiguous().to(torch.float64), rtol=ctx.rtol,
+                                          max_cycles=ctx.max_cycles)
+        return lam, None, None, None

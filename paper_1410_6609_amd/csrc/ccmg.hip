@@ -1,0 +1,929 @@
+// Host side of the cell-centered multigrid Poisson solver: hierarchy set-up,
+// workspace carving, cycle driver and the C ABI declared in include/ccmg.h.
+//
+// Design (MI355X): all level arrays live in one caller-owned workspace; every
+// smoother pass reads one buffer and writes the other (ping-pong), so a pass
+// can fuse several red-black half-sweeps with the residual, the restriction or
+// the prolongation without racing against neighbouring tiles.  The V-cycle of
+// Sec. 3 / Sec. 5.3 becomes, per level: one or two fused pre-smoothing passes
+// (the last one also restricts the residual), the coarsest-grid CG, and one or
+// two fused post-smoothing passes (the first one adds the magnified coarse
+// correction on the fly, the finest-level last one also reduces the residual
+// norm).  Cycles are enqueued in batches; a device-side flag set by the norm
+// reduction makes the remaining kernels of a batch return at once, so the
+// host reads the control block once per batch instead of once per cycle.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ccmg.h"
+#include "ccmg_kernels.hpp"
+
+using namespace ccmg;
+
+namespace {
+
+// tile shape of the smoother pass: 64 lanes along x, M rows per thread, WY waves
+constexpr int kM = 4;
+constexpr int kWY = 8;
+constexpr int kTargetBlocks = 1024;
+
+struct LevelBuf {
+    int nx = 0, ny = 0, nz = 0;
+    size_t n = 0;
+    double* phi = nullptr;   // FP64 home buffer (level 0: the caller's phi)
+    double* tmp = nullptr;   // FP64 ping-pong partner
+    double* b = nullptr;     // FP64 b-tilde
+    float* phi32 = nullptr;  // FP32 hierarchy (FP32-IR)
+    float* tmp32 = nullptr;
+    float* b32 = nullptr;
+};
+
+struct Grid {
+    int tiles_x, tiles_y, zchunks, zc;
+    int blocks() const { return tiles_x * tiles_y * zchunks; }
+};
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// tile-and-chunk decomposition of one pass over an nx*ny*nz level
+Grid pass_grid(int nx, int ny, int nz, int tx, int ty)
+{
+    Grid g;
+    g.tiles_x = cdiv(nx, tx);
+    g.tiles_y = cdiv(ny, ty);
+    const int xy = g.tiles_x * g.tiles_y;
+    int chunks = std::max(1, kTargetBlocks / xy);
+    int zc = cdiv(nz, chunks);
+    zc = std::max(8, zc + (zc & 1));      // even, and long enough to amortise the z halo
+    zc = std::min(zc, nz + (nz & 1));
+    g.zc = zc;
+    g.zchunks = cdiv(nz, zc);
+    return g;
+}
+
+}  // namespace
+
+struct ccmg_solver {
+    int nx, ny, nz;
+    double h;
+    ccmg_face bc[6];
+    int sh[6];
+    ccmg_options opt;
+    hipStream_t stream = nullptr;
+    int L = 0;
+    LevelBuf lv[CCMG_MAX_LEVELS];
+    int cg_maxit = 0;
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t need_bytes = 0;
+    Ctl* ctl = nullptr;
+    double* partials = nullptr;
+    int max_partials = 0;
+    // host mirrors
+    std::vector<double> hist;
+    int last_cycles = 0;
+    std::string err;
+};
+
+namespace {
+
+std::string g_create_err;
+
+int fail(ccmg_solver* s, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (s) s->err = buf; else g_create_err = buf;
+    return code;
+}
+
+#define HIPCHK(s, call)                                                                    \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) return fail((s), CCMG_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCHCHK(s)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = hipGetLastError();                                                 \
+        if (e_ != hipSuccess) return fail((s), CCMG_E_HIP, "kernel launch: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_device_ptr(const void* p)
+{
+    if (p == nullptr) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------------
+// pass dispatch: only the (stages, load, residual) combinations the driver
+// uses are instantiated
+// ---------------------------------------------------------------------------
+template <typename T, int SPHI, int LOAD, int RES>
+void launch_one(const PassParams<T>& P0, hipStream_t st)
+{
+    using Sh = PassShape<T, SPHI, RES, kM, kWY>;
+    PassParams<T> P = P0;
+    const Grid g = pass_grid(P.nx, P.ny, P.nz, Sh::TX, Sh::TY);
+    P.tiles_x = g.tiles_x;
+    P.tiles_y = g.tiles_y;
+    P.zchunks = g.zchunks;
+    P.zc = g.zc;
+    hipLaunchKernelGGL((k_pass<T, SPHI, LOAD, RES, kM, kWY>), dim3(g.blocks()), dim3(64 * kWY), 0, st, P);
+}
+
+template <typename T>
+int pass_blocks(int sphi, int res, int nx, int ny, int nz)
+{
+    auto blocks = [&](int S) {
+        const int H = (S + 1) & ~1;
+        return pass_grid(nx, ny, nz, 64 - 2 * H, kM * kWY - 2 * H).blocks();
+    };
+    return blocks(sphi + (res != RES_NONE ? 1 : 0));
+}
+
+template <typename T, int SPHI>
+bool dispatch_sphi(int load, int res, const PassParams<T>& P, hipStream_t st)
+{
+    switch (load) {
+    case LOAD_PHI:
+        switch (res) {
+        case RES_NONE: launch_one<T, SPHI, LOAD_PHI, RES_NONE>(P, st); return true;
+        case RES_RESTRICT: launch_one<T, SPHI, LOAD_PHI, RES_RESTRICT>(P, st); return true;
+        case RES_NORM: launch_one<T, SPHI, LOAD_PHI, RES_NORM>(P, st); return true;
+        default: return false;
+        }
+    case LOAD_ZERO:
+        switch (res) {
+        case RES_NONE: launch_one<T, SPHI, LOAD_ZERO, RES_NONE>(P, st); return true;
+        case RES_RESTRICT: launch_one<T, SPHI, LOAD_ZERO, RES_RESTRICT>(P, st); return true;
+        default: return false;
+        }
+    case LOAD_PROLONG:
+        switch (res) {
+        case RES_NONE: launch_one<T, SPHI, LOAD_PROLONG, RES_NONE>(P, st); return true;
+        case RES_RESTRICT: launch_one<T, SPHI, LOAD_PROLONG, RES_RESTRICT>(P, st); return true;
+        case RES_NORM: launch_one<T, SPHI, LOAD_PROLONG, RES_NORM>(P, st); return true;
+        default: return false;
+        }
+    default: return false;
+    }
+}
+
+template <typename T>
+bool dispatch(int sphi, int load, int res, const PassParams<T>& P, hipStream_t st);
+
+template <>
+bool dispatch<double>(int sphi, int load, int res, const PassParams<double>& P, hipStream_t st)
+{
+    if (sphi == 0) {
+        if (load == LOAD_PHI && res == RES_NORM) { launch_one<double, 0, LOAD_PHI, RES_NORM>(P, st); return true; }
+        if (load == LOAD_PHI && res == RES_STORE) { launch_one<double, 0, LOAD_PHI, RES_STORE>(P, st); return true; }
+        if (load == LOAD_PHI && res == RES_NORM_R32) { launch_one<double, 0, LOAD_PHI, RES_NORM_R32>(P, st); return true; }
+        if (load == LOAD_CORR && res == RES_NORM_R32) { launch_one<double, 0, LOAD_CORR, RES_NORM_R32>(P, st); return true; }
+        return false;
+    }
+    if (sphi == 2) return dispatch_sphi<double, 2>(load, res, P, st);
+    if (sphi == 4) return dispatch_sphi<double, 4>(load, res, P, st);
+    return false;
+}
+
+template <>
+bool dispatch<float>(int sphi, int load, int res, const PassParams<float>& P, hipStream_t st)
+{
+    if (res == RES_NORM) return false;
+    if (sphi == 2) return dispatch_sphi<float, 2>(load, res, P, st);
+    if (sphi == 4) return dispatch_sphi<float, 4>(load, res, P, st);
+    return false;
+}
+
+template <typename T>
+void launch_cg(const T* b, T* x, int nx, int ny, int nz, const int* sh, double rtol, int maxit, Ctl* ctl,
+               hipStream_t st)
+{
+    const int n = nx * ny * nz;
+    const int npt = cdiv(n, kCgThreads);
+#define CG_CASE(N)                                                                                          \
+    hipLaunchKernelGGL((k_coarse_cg<T, N>), dim3(1), dim3(kCgThreads), 0, st, b, x, nx, ny, nz, sh[0], sh[1], \
+                       sh[2], sh[3], sh[4], sh[5], rtol, maxit, ctl)
+    if (npt <= 1) CG_CASE(1);
+    else if (npt <= 2) CG_CASE(2);
+    else if (npt <= 4) CG_CASE(4);
+    else if (npt <= 8) CG_CASE(8);
+    else CG_CASE(16);
+#undef CG_CASE
+}
+
+int grid1d(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 8192); }
+
+// ---------------------------------------------------------------------------
+// one level's kernel list: pre-smoothing passes (last one restricts), then
+// post-smoothing passes (first one prolongates), with ping-pong buffers
+// ---------------------------------------------------------------------------
+struct PassSpec {
+    int sphi;   // half-sweeps in this pass
+    int load;
+    int res;
+};
+
+std::vector<PassSpec> level_passes(int nu1, int nu2, int fuse, bool first_zero, int post_last_res)
+{
+    std::vector<PassSpec> v;
+    int left = nu1;
+    bool first = true;
+    while (left > 0) {
+        const int k = std::min(fuse, left);
+        left -= k;
+        v.push_back({2 * k, first ? (first_zero ? LOAD_ZERO : LOAD_PHI) : LOAD_PHI, left == 0 ? RES_RESTRICT : RES_NONE});
+        first = false;
+    }
+    left = nu2;
+    first = true;
+    while (left > 0) {
+        const int k = std::min(fuse, left);
+        left -= k;
+        v.push_back({2 * k, first ? LOAD_PROLONG : LOAD_PHI, left == 0 ? post_last_res : RES_NONE});
+        first = false;
+    }
+    return v;
+}
+
+// Destination buffer of every pass of a level so that the level ends in its
+// home buffer.  Returns true if a final copy tmp -> home is needed.
+bool assign_dst(int nk, bool first_src_is_home, std::vector<int>& dst_is_home)
+{
+    dst_is_home.assign(nk, 0);
+    if (!first_src_is_home || nk % 2 == 0) {
+        for (int i = nk - 1, h = 1; i >= 0; --i, h ^= 1) dst_is_home[i] = h;
+        return false;
+    }
+    for (int i = 0, h = 0; i < nk; ++i, h ^= 1) dst_is_home[i] = h;
+    return true;
+}
+
+template <typename T>
+struct LevelPtrs {
+    T* home[CCMG_MAX_LEVELS];
+    T* tmp[CCMG_MAX_LEVELS];
+    T* b[CCMG_MAX_LEVELS];
+};
+
+template <typename T>
+PassParams<T> base_params(const ccmg_solver* s, int l)
+{
+    PassParams<T> P;
+    std::memset(&P, 0, sizeof P);
+    P.nx = s->lv[l].nx;
+    P.ny = s->lv[l].ny;
+    P.nz = s->lv[l].nz;
+    for (int f = 0; f < 6; ++f) P.sh[f] = s->sh[f];
+    P.ctl = s->ctl;
+    P.partials = s->partials;
+    P.omega = (T)s->opt.omega;
+    return P;
+}
+
+// Enqueue one V-cycle over levels l0..L-1 of the hierarchy `H` (type T).
+// Level l0 starts from its home buffer (or from zero if l0_zero) and ends in
+// it.  If fin_cycle > 0, the last pass of level l0 reduces the residual norm
+// and finalises cycle `fin_cycle`.
+template <typename T>
+int enqueue_vcycle(ccmg_solver* s, const LevelPtrs<T>& H, bool l0_zero, int fin_cycle)
+{
+    const int L = s->L;
+    const int fuse = s->opt.fuse_sweeps;
+    hipStream_t st = s->stream;
+    // descend
+    struct Pending { std::vector<PassSpec> ps; std::vector<int> dh; bool copy; size_t next; };
+    Pending pend[CCMG_MAX_LEVELS];
+    for (int l = 0; l < L - 1; ++l) {
+        const bool zero = (l > 0) || l0_zero;
+        const int post_res = (l == 0 && fin_cycle > 0) ? RES_NORM : RES_NONE;
+        pend[l].ps = level_passes(s->opt.nu1, s->opt.nu2, fuse, zero, post_res);
+        pend[l].copy = assign_dst((int)pend[l].ps.size(), !zero, pend[l].dh);
+        pend[l].next = 0;
+        // pre-smoothing passes
+        T* cur = zero ? nullptr : H.home[l];
+        for (size_t i = 0; i < pend[l].ps.size(); ++i) {
+            const PassSpec& p = pend[l].ps[i];
+            if (p.load == LOAD_PROLONG) break;
+            PassParams<T> P = base_params<T>(s, l);
+            P.phi_in = cur;
+            P.b = H.b[l];
+            P.phi_out = pend[l].dh[i] ? H.home[l] : H.tmp[l];
+            P.bc_out = H.b[l + 1];
+            if (!dispatch<T>(p.sphi, p.load, p.res, P, st))
+                return fail(s, CCMG_E_ARG, "unsupported smoother pass (%d,%d,%d)", p.sphi, p.load, p.res);
+            cur = P.phi_out;
+            pend[l].next = i + 1;
+        }
+    }
+    // coarsest level
+    {
+        const int l = L - 1;
+        const LevelBuf& B = s->lv[l];
+        launch_cg<T>(H.b[l], H.home[l], B.nx, B.ny, B.nz, s->sh, s->opt.cg_rtol, s->cg_maxit, s->ctl, st);
+    }
+    // ascend
+    for (int l = L - 2; l >= 0; --l) {
+        Pending& pd = pend[l];
+        T* cur = (pd.next > 0) ? (pd.dh[pd.next - 1] ? H.home[l] : H.tmp[l]) : H.home[l];
+        for (size_t i = pd.next; i < pd.ps.size(); ++i) {
+            const PassSpec& p = pd.ps[i];
+            PassParams<T> P = base_params<T>(s, l);
+            P.phi_in = cur;
+            P.b = H.b[l];
+            P.ec = H.home[l + 1];
+            P.phi_out = pd.dh[i] ? H.home[l] : H.tmp[l];
+            if (p.res == RES_NORM) {
+                P.fin = FIN_CYCLE;
+                P.cycle = fin_cycle;
+            }
+            if (!dispatch<T>(p.sphi, p.load, p.res, P, st))
+                return fail(s, CCMG_E_ARG, "unsupported smoother pass (%d,%d,%d)", p.sphi, p.load, p.res);
+            cur = P.phi_out;
+        }
+        if (pd.copy) {
+            const size_t n = s->lv[l].n;
+            // level 0: the norm pass of this cycle may just have set `done`, so this copy always runs
+            hipLaunchKernelGGL((k_copy<T>), dim3(grid1d(n)), dim3(256), 0, st, (const T*)H.tmp[l], H.home[l], n,
+                               l == 0 ? (const Ctl*)nullptr : (const Ctl*)s->ctl);
+        }
+    }
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+LevelPtrs<double> fp64_ptrs(ccmg_solver* s, double* phi0)
+{
+    LevelPtrs<double> H;
+    for (int l = 0; l < s->L; ++l) {
+        H.home[l] = l == 0 ? phi0 : s->lv[l].phi;
+        H.tmp[l] = s->lv[l].tmp;
+        H.b[l] = s->lv[l].b;
+    }
+    return H;
+}
+
+LevelPtrs<float> fp32_ptrs(ccmg_solver* s)
+{
+    LevelPtrs<float> H;
+    for (int l = 0; l < s->L; ++l) {
+        H.home[l] = s->lv[l].phi32;
+        H.tmp[l] = s->lv[l].tmp32;
+        H.b[l] = s->lv[l].b32;
+    }
+    return H;
+}
+
+int enqueue_ctl_init(ccmg_solver* s, double rtol)
+{
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s->stream, s->ctl, rtol);
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+// b-tilde_0 = h^2 (f + boundary terms); homogeneous=true drops the boundary values
+int enqueue_fold(ccmg_solver* s, const double* f, bool homogeneous)
+{
+    const LevelBuf& B = s->lv[0];
+    double t[6];
+    for (int fc = 0; fc < 6; ++fc) {
+        const double g = homogeneous ? 0.0 : s->bc[fc].value;
+        t[fc] = s->bc[fc].kind == CCMG_DIRICHLET ? 2.0 * g / (s->h * s->h) : g / s->h;
+    }
+    hipLaunchKernelGGL(k_fold, dim3(grid1d(B.n)), dim3(256), 0, s->stream, f, B.b, B.nx, B.ny, B.nz, s->h * s->h,
+                       t[0], t[1], t[2], t[3], t[4], t[5], s->ctl);
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+// residual-norm pass on the finest level (FP64) finalised as `fin`
+int enqueue_norm(ccmg_solver* s, const double* phi, int fin, int res, double* r_out, float* r32_out, int cycle)
+{
+    PassParams<double> P = base_params<double>(s, 0);
+    P.phi_in = phi;
+    P.b = s->lv[0].b;
+    P.fin = fin;
+    P.cycle = cycle;
+    P.r_out = r_out;
+    P.r32_out = r32_out;
+    if (!dispatch<double>(0, LOAD_PHI, res, P, s->stream)) return fail(s, CCMG_E_ARG, "norm pass");
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+struct CtlHead {
+    double rtol, bnorm, rnorm, rel, sig_cur, sig_next;
+    int done, status, cycles, bzero;
+    unsigned counter;
+    int cg_iters;
+    int pad[2];
+};
+static_assert(sizeof(CtlHead) == offsetof(Ctl, hist), "control block header layout");
+
+int read_ctl(ccmg_solver* s, CtlHead& h, int hist_upto)
+{
+    HIPCHK(s, hipMemcpyAsync(&h, s->ctl, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    if (hist_upto >= 0) {
+        const int n = std::min(hist_upto + 1, kMaxHist);
+        s->hist.resize(n);
+        HIPCHK(s, hipMemcpy(s->hist.data(), s->ctl->hist, n * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return CCMG_OK;
+}
+
+// Run the cycle loop after the initial residual pass.  `enqueue_step(k)`
+// enqueues cycle / refinement step k (k >= 1) ending with FIN_CYCLE(k).
+template <typename F>
+int run_loop(ccmg_solver* s, int max_cycles, F enqueue_step, CtlHead& h)
+{
+    int k = 0;
+    int rc = read_ctl(s, h, -1);   // initial state (also catches a zero RHS)
+    if (rc) return rc;
+    if (h.done) return CCMG_OK;
+    int batch = s->last_cycles > 0 ? s->last_cycles : 8;
+    while (k < max_cycles) {
+        batch = std::max(1, std::min(batch, max_cycles - k));
+        for (int i = 0; i < batch; ++i) {
+            rc = enqueue_step(k + 1 + i);
+            if (rc) return rc;
+        }
+        k += batch;
+        rc = read_ctl(s, h, -1);
+        if (rc) return rc;
+        if (h.done) break;
+        // estimate the remaining cycles from the observed contraction
+        std::vector<double> hv(2);
+        const int c = h.cycles;
+        HIPCHK(s, hipMemcpy(hv.data(), s->ctl->hist + (c - 1), 2 * sizeof(double), hipMemcpyDeviceToHost));
+        const double rate = (hv[0] > 0.0) ? hv[1] / hv[0] : 0.5;
+        int need = 2;
+        if (rate > 0.0 && rate < 1.0 && h.rel > 0.0)
+            need = (int)std::ceil(std::log(h.rtol / h.rel) / std::log(rate));
+        batch = std::max(1, std::min(need, 64));
+    }
+    return CCMG_OK;
+}
+
+int finish_stats(ccmg_solver* s, const CtlHead& h, int inner_per_step, ccmg_stats* st,
+                 std::chrono::steady_clock::time_point t0)
+{
+    int rc = read_ctl(s, const_cast<CtlHead&>(h), h.cycles);
+    if (rc) return rc;
+    s->last_cycles = h.cycles > 0 ? h.cycles : s->last_cycles;
+    if (st) {
+        st->cycles = h.cycles;
+        st->inner_cycles = h.cycles * inner_per_step;
+        st->rel_res0 = s->hist.empty() ? 0.0 : s->hist[0];
+        st->rel_res = h.rel;
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (h.status == -5) return fail(s, CCMG_E_NONFINITE, "residual is not finite after %d cycles", h.cycles);
+    if (!h.done) return fail(s, CCMG_E_NOCONV, "relative residual %.3e >= rtol after %d cycles", h.rel, h.cycles);
+    return CCMG_OK;
+}
+
+// Whole solve on b-tilde_0 already in the workspace.  phi: initial guess in,
+// solution out.
+int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_stats* st,
+                 std::chrono::steady_clock::time_point t0)
+{
+    int rc = enqueue_norm(s, phi, FIN_INIT, RES_NORM, nullptr, nullptr, 0);
+    if (rc) return rc;
+    const LevelBuf& B0 = s->lv[0];
+    hipLaunchKernelGGL(k_zero_if_bzero, dim3(grid1d(B0.n)), dim3(256), 0, s->stream, phi, B0.n, (const Ctl*)s->ctl);
+    LAUNCHCHK(s);
+    CtlHead h;
+    int inner = 1;
+    if (s->opt.precision == CCMG_FP64) {
+        const LevelPtrs<double> H = fp64_ptrs(s, phi);
+        rc = run_loop(s, max_cycles, [&](int k) { return enqueue_vcycle<double>(s, H, false, k); }, h);
+    } else {
+        inner = s->opt.ir_inner_cycles;
+        const LevelPtrs<float> H = fp32_ptrs(s);
+        // first scaled FP32 residual of the initial guess (re-finalises cycle 0)
+        rc = enqueue_norm(s, phi, FIN_CYCLE, RES_NORM_R32, nullptr, s->lv[0].b32, 0);
+        if (rc) return rc;
+        double* tmp = s->lv[0].tmp;
+        // step k reads the iterate from phi (k odd) or tmp (k even) and writes the other one
+        auto step = [&](int k) -> int {
+            for (int m = 0; m < inner; ++m) {
+                int r = enqueue_vcycle<float>(s, H, m == 0, 0);
+                if (r) return r;
+            }
+            PassParams<double> P = base_params<double>(s, 0);
+            P.phi_in = (k & 1) ? phi : tmp;
+            P.phi_out = (k & 1) ? tmp : phi;
+            P.b = s->lv[0].b;
+            P.corr = s->lv[0].phi32;
+            P.r32_out = s->lv[0].b32;
+            P.fin = FIN_CYCLE;
+            P.cycle = k;
+            if (!dispatch<double>(0, LOAD_CORR, RES_NORM_R32, P, s->stream)) return fail(s, CCMG_E_ARG, "IR pass");
+            LAUNCHCHK(s);
+            return CCMG_OK;
+        };
+        rc = run_loop(s, max_cycles, step, h);
+        if (rc) return rc;
+        if (h.cycles & 1) {
+            // the last finished step left the iterate in tmp
+            hipLaunchKernelGGL((k_copy<double>), dim3(grid1d(B0.n)), dim3(256), 0, s->stream, (const double*)tmp, phi,
+                               B0.n, (const Ctl*)nullptr);
+            LAUNCHCHK(s);
+        }
+    }
+    if (rc) return rc;
+    return finish_stats(s, h, inner, st, t0);
+}
+
+// Carve the workspace: control block, norm partials, then per level the
+// FP64 b-tilde / ping-pong / home buffers (finest level, and every level in
+// FP64 mode) and the FP32 hierarchy (FP32-IR mode).  With base == nullptr
+// only the size is computed.  Returns the bytes used.
+size_t layout_workspace(ccmg_solver* s, char* base)
+{
+    size_t off = 0;
+    auto take = [&](size_t b) -> char* { char* p = base ? base + off : nullptr; off += align256(b); return p; };
+    Ctl* ctl = (Ctl*)take(sizeof(Ctl));
+    double* part = (double*)take(2 * sizeof(double) * (size_t)s->max_partials);
+    if (base) { s->ctl = ctl; s->partials = part; }
+    for (int l = 0; l < s->L; ++l) {
+        LevelBuf& B = s->lv[l];
+        const size_t n = B.n;
+        double *b = nullptr, *tmp = nullptr, *phi = nullptr;
+        float *b32 = nullptr, *tmp32 = nullptr, *phi32 = nullptr;
+        if (l == 0 || s->opt.precision == CCMG_FP64) {
+            b = (double*)take(n * 8);
+            tmp = (double*)take(n * 8);
+            if (l > 0) phi = (double*)take(n * 8);
+        }
+        if (s->opt.precision == CCMG_FP32_IR) {
+            b32 = (float*)take(n * 4);
+            tmp32 = (float*)take(n * 4);
+            phi32 = (float*)take(n * 4);
+        }
+        if (base) {
+            B.b = b; B.tmp = tmp; B.phi = phi;
+            B.b32 = b32; B.tmp32 = tmp32; B.phi32 = phi32;
+        }
+    }
+    return off;
+}
+
+int check_ready(ccmg_solver* s)
+{
+    if (s == nullptr) return CCMG_E_ARG;
+    if (s->ws == nullptr) return fail(s, CCMG_E_STATE, "no workspace attached");
+    return CCMG_OK;
+}
+
+#define NEED_DEV(s, p, name)                                                              \
+    do {                                                                                  \
+        if (!is_device_ptr(p)) return fail((s), CCMG_E_ARG, "%s must be device memory", name); \
+    } while (0)
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+void ccmg_default_options(ccmg_options* o)
+{
+    if (!o) return;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->levels = 0;
+    o->omega = 2.0;
+    o->precision = CCMG_FP64;
+    o->ir_inner_cycles = 2;
+    o->cg_rtol = 1e-13;
+    o->cg_maxit = 0;
+    o->fuse_sweeps = 2;
+}
+
+int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_face bc[6],
+                const ccmg_options* opt, void* hip_stream)
+{
+    g_create_err.clear();
+    if (!out || !bc) return fail(nullptr, CCMG_E_ARG, "null argument");
+    *out = nullptr;
+    if (nx < 2 || ny < 2 || nz < 2) return fail(nullptr, CCMG_E_ARG, "grid must be at least 2 cells per axis");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(nullptr, CCMG_E_ARG, "spacing must be positive");
+    ccmg_options o;
+    ccmg_default_options(&o);
+    if (opt) o = *opt;
+    if (o.nu1 < 1 || o.nu1 > 8 || o.nu2 < 1 || o.nu2 > 8) return fail(nullptr, CCMG_E_ARG, "nu1, nu2 must be in 1..8");
+    if (o.precision != CCMG_FP64 && o.precision != CCMG_FP32_IR) return fail(nullptr, CCMG_E_ARG, "bad precision");
+    if (o.ir_inner_cycles < 1 || o.ir_inner_cycles > 16) return fail(nullptr, CCMG_E_ARG, "ir_inner_cycles in 1..16");
+    if (o.fuse_sweeps != 1 && o.fuse_sweeps != 2) return fail(nullptr, CCMG_E_ARG, "fuse_sweeps must be 1 or 2");
+    if (!(o.cg_rtol > 0.0) || o.cg_maxit < 0) return fail(nullptr, CCMG_E_ARG, "bad CG options");
+    if (!std::isfinite(o.omega)) return fail(nullptr, CCMG_E_ARG, "bad omega");
+    bool any_dirichlet = false;
+    for (int f = 0; f < 6; ++f) {
+        if (bc[f].kind != CCMG_DIRICHLET && bc[f].kind != CCMG_NEUMANN) return fail(nullptr, CCMG_E_ARG, "bad face kind");
+        if (!std::isfinite(bc[f].value)) return fail(nullptr, CCMG_E_ARG, "face value not finite");
+        any_dirichlet |= bc[f].kind == CCMG_DIRICHLET;
+    }
+    if (!any_dirichlet) return fail(nullptr, CCMG_E_SINGULAR, "all faces Neumann: the operator is singular");
+    // hierarchy depth
+    int L = o.levels;
+    if (L == 0) {
+        L = 1;
+        int a = nx, b = ny, c = nz;
+        while ((size_t)a * b * c > 512 && a % 2 == 0 && b % 2 == 0 && c % 2 == 0 && a >= 4 && b >= 4 && c >= 4 &&
+               L < CCMG_MAX_LEVELS) {
+            a /= 2; b /= 2; c /= 2;
+            ++L;
+        }
+    }
+    if (L < 2 || L > CCMG_MAX_LEVELS) return fail(nullptr, CCMG_E_DIMS, "levels must be in 2..%d", CCMG_MAX_LEVELS);
+    const int div = 1 << (L - 1);
+    if (nx % div || ny % div || nz % div)
+        return fail(nullptr, CCMG_E_DIMS, "dims %dx%dx%d not divisible by 2^(levels-1) = %d", nx, ny, nz, div);
+    const size_t ncoarse = (size_t)(nx / div) * (ny / div) * (nz / div);
+    if (ncoarse > CCMG_MAX_COARSE_CELLS)
+        return fail(nullptr, CCMG_E_DIMS, "coarsest grid has %zu cells (max %d): use more levels", ncoarse,
+                    CCMG_MAX_COARSE_CELLS);
+    if ((size_t)nx * ny * nz > (size_t)1 << 34) return fail(nullptr, CCMG_E_DIMS, "grid too large");
+
+    ccmg_solver* s = new ccmg_solver();
+    s->nx = nx; s->ny = ny; s->nz = nz; s->h = h;
+    for (int f = 0; f < 6; ++f) {
+        s->bc[f] = bc[f];
+        s->sh[f] = bc[f].kind == CCMG_DIRICHLET ? 1 : -1;
+    }
+    s->opt = o;
+    s->opt.levels = L;
+    s->stream = (hipStream_t)hip_stream;
+    s->L = L;
+    s->cg_maxit = o.cg_maxit > 0 ? o.cg_maxit : (int)(2 * ncoarse);
+
+    int maxb = 0;
+    for (int sphi : {0, 2, 4})
+        for (int res : {RES_NONE, RES_NORM})
+            maxb = std::max(maxb, pass_blocks<double>(sphi, res, nx, ny, nz));
+    s->max_partials = maxb;
+    for (int l = 0; l < L; ++l) {
+        LevelBuf& B = s->lv[l];
+        B.nx = nx >> l; B.ny = ny >> l; B.nz = nz >> l;
+        B.n = (size_t)B.nx * B.ny * B.nz;
+    }
+    s->need_bytes = layout_workspace(s, nullptr);
+    *out = s;
+    return CCMG_OK;
+}
+
+size_t ccmg_workspace_bytes(const ccmg_solver* s) { return s ? s->need_bytes : 0; }
+
+int ccmg_set_workspace(ccmg_solver* s, void* d_ptr, size_t bytes)
+{
+    if (!s) return CCMG_E_ARG;
+    if (!d_ptr) return fail(s, CCMG_E_ARG, "null workspace");
+    if (((uintptr_t)d_ptr & 255) != 0) return fail(s, CCMG_E_ARG, "workspace must be 256-byte aligned");
+    if (bytes < s->need_bytes) return fail(s, CCMG_E_STATE, "workspace of %zu bytes, need %zu", bytes, s->need_bytes);
+    NEED_DEV(s, d_ptr, "workspace");
+    char* base = (char*)d_ptr;
+    if (layout_workspace(s, base) != s->need_bytes) return fail(s, CCMG_E_STATE, "internal: workspace layout mismatch");
+    s->ws = base;
+    s->ws_bytes = bytes;
+    return CCMG_OK;
+}
+
+int ccmg_set_stream(ccmg_solver* s, void* hip_stream)
+{
+    if (!s) return CCMG_E_ARG;
+    s->stream = (hipStream_t)hip_stream;
+    return CCMG_OK;
+}
+
+int ccmg_num_levels(const ccmg_solver* s) { return s ? s->L : 0; }
+
+int ccmg_level_dims(const ccmg_solver* s, int l, int dims_out[3])
+{
+    if (!s || !dims_out || l < 0 || l >= s->L) return CCMG_E_ARG;
+    dims_out[0] = s->lv[l].nx;
+    dims_out[1] = s->lv[l].ny;
+    dims_out[2] = s->lv[l].nz;
+    return CCMG_OK;
+}
+
+int ccmg_deposit_charges(ccmg_solver* s, int n, const double* d_centers, const double* d_radii, const double* d_q,
+                         double eps, double* d_f, int* d_counts)
+{
+    if (!s) return CCMG_E_ARG;
+    s->err.clear();
+    if (n < 0) return fail(s, CCMG_E_ARG, "negative sphere count");
+    if (!(eps > 0.0)) return fail(s, CCMG_E_ARG, "eps must be positive");
+    NEED_DEV(s, d_f, "d_f");
+    const LevelBuf& B = s->lv[0];
+    hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(B.n)), dim3(256), 0, s->stream, d_f, B.n, 0.0);
+    if (n > 0) {
+        NEED_DEV(s, d_centers, "d_centers");
+        NEED_DEV(s, d_radii, "d_radii");
+        NEED_DEV(s, d_q, "d_q");
+        if (d_counts) NEED_DEV(s, d_counts, "d_counts");
+        hipLaunchKernelGGL(k_deposit, dim3(n), dim3(kSphereThreads), 0, s->stream, d_centers, d_radii, d_q, eps, s->h,
+                           B.nx, B.ny, B.nz, d_f, d_counts);
+    }
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+int ccmg_vcycle(ccmg_solver* s, double* d_phi, const double* d_f, double* rel_res_out)
+{
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    NEED_DEV(s, d_phi, "d_phi");
+    NEED_DEV(s, d_f, "d_f");
+    if ((rc = enqueue_ctl_init(s, -1.0))) return rc;
+    if ((rc = enqueue_fold(s, d_f, false))) return rc;
+    if (s->opt.precision == CCMG_FP64) {
+        rc = enqueue_vcycle<double>(s, fp64_ptrs(s, d_phi), false, rel_res_out ? 1 : 0);
+        if (rc) return rc;
+    } else {
+        // one refinement step: FP32 cycles on the scaled residual, FP64 update
+        if ((rc = enqueue_norm(s, d_phi, FIN_INIT, RES_NORM, nullptr, nullptr, 0))) return rc;
+        if ((rc = enqueue_norm(s, d_phi, FIN_CYCLE, RES_NORM_R32, nullptr, s->lv[0].b32, 0))) return rc;
+        const LevelPtrs<float> H = fp32_ptrs(s);
+        for (int m = 0; m < s->opt.ir_inner_cycles; ++m)
+            if ((rc = enqueue_vcycle<float>(s, H, m == 0, 0))) return rc;
+        PassParams<double> P = base_params<double>(s, 0);
+        P.phi_in = d_phi;
+        P.phi_out = s->lv[0].tmp;
+        P.b = s->lv[0].b;
+        P.corr = s->lv[0].phi32;
+        P.r32_out = s->lv[0].b32;
+        P.fin = FIN_CYCLE;
+        P.cycle = 1;
+        if (!dispatch<double>(0, LOAD_CORR, RES_NORM_R32, P, s->stream)) return fail(s, CCMG_E_ARG, "IR pass");
+        const size_t n = s->lv[0].n;
+        hipLaunchKernelGGL((k_copy<double>), dim3(grid1d(n)), dim3(256), 0, s->stream, (const double*)s->lv[0].tmp,
+                           d_phi, n, (const Ctl*)nullptr);
+        LAUNCHCHK(s);
+    }
+    if (rel_res_out) {
+        CtlHead h;
+        if ((rc = read_ctl(s, h, -1))) return rc;
+        *rel_res_out = h.rel;
+        if (h.status == -5) return fail(s, CCMG_E_NONFINITE, "residual is not finite");
+    }
+    return CCMG_OK;
+}
+
+int ccmg_solve(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles, ccmg_stats* st)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    if (max_cycles < 0 || max_cycles > CCMG_MAX_CYCLES) return fail(s, CCMG_E_ARG, "max_cycles out of range");
+    if (!(rtol >= 0.0)) return fail(s, CCMG_E_ARG, "rtol must be >= 0");
+    NEED_DEV(s, d_phi, "d_phi");
+    NEED_DEV(s, d_f, "d_f");
+    if ((rc = enqueue_ctl_init(s, rtol))) return rc;
+    if ((rc = enqueue_fold(s, d_f, false))) return rc;
+    return solve_folded(s, d_phi, rtol, max_cycles, st, t0);
+}
+
+int ccmg_adjoint_solve(ccmg_solver* s, const double* d_g, double* d_lambda, int n, const double* d_centers,
+                       const double* d_radii, double eps, double* d_dq, double* d_drho, double rtol, int max_cycles,
+                       ccmg_stats* st)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    if (max_cycles < 0 || max_cycles > CCMG_MAX_CYCLES) return fail(s, CCMG_E_ARG, "max_cycles out of range");
+    if (!(rtol >= 0.0)) return fail(s, CCMG_E_ARG, "rtol must be >= 0");
+    if (n < 0) return fail(s, CCMG_E_ARG, "negative sphere count");
+    if ((d_dq || d_drho) && !(eps > 0.0)) return fail(s, CCMG_E_ARG, "eps must be positive");
+    NEED_DEV(s, d_g, "d_g");
+    NEED_DEV(s, d_lambda, "d_lambda");
+    const size_t n0 = s->lv[0].n;
+    if ((rc = enqueue_ctl_init(s, rtol))) return rc;
+    hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(n0)), dim3(256), 0, s->stream, d_lambda, n0, 0.0);
+    if ((rc = enqueue_fold(s, d_g, true))) return rc;
+    const int src = solve_folded(s, d_lambda, rtol, max_cycles, st, t0);
+    if (src != CCMG_OK && src != CCMG_E_NOCONV) return src;
+    if (d_drho) {
+        NEED_DEV(s, d_drho, "d_drho");
+        hipLaunchKernelGGL(k_scale, dim3(grid1d(n0)), dim3(256), 0, s->stream, (const double*)d_lambda, d_drho, n0,
+                           1.0 / eps);
+    }
+    if (n > 0 && d_dq) {
+        NEED_DEV(s, d_centers, "d_centers");
+        NEED_DEV(s, d_radii, "d_radii");
+        NEED_DEV(s, d_dq, "d_dq");
+        const LevelBuf& B = s->lv[0];
+        hipLaunchKernelGGL(k_dq, dim3(n), dim3(kSphereThreads), 0, s->stream, d_centers, d_radii, eps, s->h, B.nx, B.ny,
+                           B.nz, (const double*)d_lambda, d_dq);
+    }
+    LAUNCHCHK(s);
+    if (st) {
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return src;
+}
+
+int ccmg_residual(ccmg_solver* s, const double* d_phi, const double* d_f, double* d_r, double* rel_res_out)
+{
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    NEED_DEV(s, d_phi, "d_phi");
+    NEED_DEV(s, d_f, "d_f");
+    if (d_r) NEED_DEV(s, d_r, "d_r");
+    if ((rc = enqueue_ctl_init(s, -1.0))) return rc;
+    if ((rc = enqueue_fold(s, d_f, false))) return rc;
+    PassParams<double> P = base_params<double>(s, 0);
+    P.phi_in = d_phi;
+    P.b = s->lv[0].b;
+    P.fin = FIN_STORE;
+    P.r_out = d_r;
+    P.rscale = 1.0 / (s->h * s->h);
+    if (!dispatch<double>(0, LOAD_PHI, RES_STORE, P, s->stream)) return fail(s, CCMG_E_ARG, "residual pass");
+    LAUNCHCHK(s);
+    if (rel_res_out) {
+        CtlHead h;
+        if ((rc = read_ctl(s, h, -1))) return rc;
+        *rel_res_out = h.rel;
+    }
+    return CCMG_OK;
+}
+
+int ccmg_smooth(ccmg_solver* s, double* d_phi, const double* d_f, int sweeps)
+{
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    if (sweeps < 0) return fail(s, CCMG_E_ARG, "negative sweep count");
+    NEED_DEV(s, d_phi, "d_phi");
+    NEED_DEV(s, d_f, "d_f");
+    if (sweeps == 0) return CCMG_OK;
+    if ((rc = enqueue_ctl_init(s, -1.0))) return rc;
+    if ((rc = enqueue_fold(s, d_f, false))) return rc;
+    const int fuse = s->opt.fuse_sweeps;
+    std::vector<PassSpec> ps;
+    for (int left = sweeps; left > 0;) {
+        const int k = std::min(fuse, left);
+        left -= k;
+        ps.push_back({2 * k, LOAD_PHI, RES_NONE});
+    }
+    std::vector<int> dh;
+    const bool copy = assign_dst((int)ps.size(), true, dh);
+    double* cur = d_phi;
+    for (size_t i = 0; i < ps.size(); ++i) {
+        PassParams<double> P = base_params<double>(s, 0);
+        P.phi_in = cur;
+        P.b = s->lv[0].b;
+        P.phi_out = dh[i] ? d_phi : s->lv[0].tmp;
+        if (!dispatch<double>(ps[i].sphi, ps[i].load, ps[i].res, P, s->stream)) return fail(s, CCMG_E_ARG, "smooth pass");
+        cur = P.phi_out;
+    }
+    if (copy) {
+        const size_t n = s->lv[0].n;
+        hipLaunchKernelGGL((k_copy<double>), dim3(grid1d(n)), dim3(256), 0, s->stream, (const double*)s->lv[0].tmp,
+                           d_phi, n, (const Ctl*)nullptr);
+    }
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+int ccmg_history(const ccmg_solver* s, double* out, int max)
+{
+    if (!s || !out || max < 0) return CCMG_E_ARG;
+    const int n = std::min<int>(max, (int)s->hist.size());
+    for (int i = 0; i < n; ++i) out[i] = s->hist[i];
+    return n;
+}
+
+const char* ccmg_last_error(const ccmg_solver* s) { return s ? s->err.c_str() : g_create_err.c_str(); }
+
+void ccmg_destroy(ccmg_solver* s) { delete s; }
+
+}  // extern "C"
