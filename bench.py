@@ -1,0 +1,202 @@
+"""Benchmark: fine-grid unknowns solved per second to a relative residual of 1e-10.
+
+One step = the whole hot path on one batch of synthetic input already resident
+in HBM: charge deposition of the spheres, boundary folding of the right-hand
+side and the multigrid solve from phi = 0 to ||b - A phi|| / ||b|| < 1e-10.
+Workload (default): 256^3 cells, Dirichlet phi = 0 / 1 on the z faces and
+zero-Neumann sides, 200 seeded charged spheres of radius 4, plain FP64
+V(2,2)-cycles down to an 8^3 coarsest grid.
+
+Prints one JSON line.  Also reports the FP32-in-FP64 refinement solve on the
+same input, the live-timed roofline of the dominant kernel and the CPU
+oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import paper_1410_6609_amd as pkg  # noqa: E402
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_solver(w: W.Workload, dev, precision=pkg.FP64, fuse=2, inner=2):
+    opt = pkg.Options(levels=w.levels, nu1=w.nu1, nu2=w.nu2, omega=w.omega, precision=precision,
+                      fuse_sweeps=fuse, ir_inner_cycles=inner)
+    return pkg.Solver(w.shape, w.h, list(zip(w.kinds, w.values)), opt, device=dev)
+
+
+def run_steps(s, sph_dev, f, phi, w, n):
+    stats = None
+    for _ in range(n):
+        s.deposit(*sph_dev, w.eps, out=f)
+        phi.zero_()
+        _, stats = s.solve(f, phi, rtol=w.rtol, max_cycles=100)
+    return stats
+
+
+def timed(s, sph_dev, f, phi, w, steps):
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    st = run_steps(s, sph_dev, f, phi, w, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / 1e3, wall, st
+
+
+def cpu_baseline(w: W.Workload, sph, budget_s: float = 12.0):
+    import oracle
+    oracle.lib()
+    cores = oracle.num_threads()
+    t0 = time.perf_counter()
+    runs = 0
+    cycles = 0
+    while True:
+        f, _ = oracle.deposit(w.shape, w.h, sph.centers, sph.radii, sph.charges, w.eps)
+        phi, hist, st = oracle.solve_problem(f, w.h, w.kinds, w.values, w.levels, rtol=w.rtol,
+                                             nu1=w.nu1, nu2=w.nu2, omega=w.omega)
+        runs += 1
+        cycles = len(hist) - 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or runs >= 3:
+            break
+    per = el / runs
+    return {"value": w.cells / per, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
+            "sample": f"{runs} full solve(s) of the same workload (deposit + fold + {cycles} V(2,2)-cycles "
+                      f"to 1e-10), {per:.2f} s each, OpenMP threads={cores}",
+            "seconds_per_solve": per}, phi
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=W.C2.name, choices=sorted(W.ALL))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ir", action="store_true", help="skip the FP32-IR comparison")
+    ap.add_argument("--fuse", type=int, default=2)
+    ap.add_argument("--inner", type=int, default=2)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain device copy of 1 GiB (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs its solver on a single MI355X "
+              "(a multi-GPU decomposition is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    dev = torch.device("cuda:0")
+    w = W.ALL[args.workload]
+    sph = W.workload_spheres(w)
+    sph_dev = tuple(torch.tensor(a, device=dev) for a in (sph.centers, sph.radii, sph.charges))
+    nx, ny, nz = w.shape
+    s = make_solver(w, dev, fuse=args.fuse)
+    f = s.zeros()
+    phi = s.zeros()
+    log(f"workload {w.name}: {w.shape} levels={s.levels} ws={s.workspace.numel() / 2**20:.0f} MiB")
+
+    run_steps(s, sph_dev, f, phi, w, args.warmup)
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    s.profile(True)
+    s.profile_read(0)
+    s.profile_read(1)
+    t_gpu, wall, st = timed(s, sph_dev, f, phi, w, args.steps)
+    ms0, n0 = s.profile_read(0)
+    ms1, n1 = s.profile_read(1)
+    s.profile(False)
+    ms_step = t_gpu / args.steps * 1e3
+    value = w.cells * args.steps / t_gpu
+    log(f"fp64: {ms_step:.3f} ms/step, {st.cycles} cycles, rel {st.rel_res:.2e}, wall {wall:.3f}s")
+
+    # roofline of the dominant kernel: the finest-level fused pass with the larger total time
+    cells = w.cells
+    passes = [
+        ("pre-smoothing pass (2 RB-GS sweeps + residual + restriction), finest level", ms0, n0,
+         8 + 8 + 8 + 1),
+        ("post-smoothing pass (prolongation + 2 RB-GS sweeps + residual norm), finest level", ms1, n1,
+         8 + 1 + 8 + 8),
+    ]
+    name, ms_k, n_k, bpc = max(passes, key=lambda p: p[1])
+    avg_s = ms_k / max(n_k, 1) / 1e3
+    bytes_per_launch = bpc * cells
+    achieved = bytes_per_launch / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_k,
+                "algorithmic_bytes_per_cell": bpc}
+    other = [p for p in passes if p[0] != name][0]
+    roofline["other_pass"] = {"kernel": other[0], "avg_launch_us": round(other[1] / max(other[2], 1) * 1e3, 2),
+                              "achieved_GBs": round(other[3] * cells / (other[1] / max(other[2], 1) / 1e3) / 1e9, 1)}
+
+    out = {
+        "metric": "fine-grid unknowns solved/s to 1e-10 rel. residual",
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded charged spheres)",
+        "config": {"workload": w.name, "cells": [nx, ny, nz], "levels": s.levels, "cycle": "V(2,2)",
+                   "coarsest": list(s.level_dims(s.levels - 1)), "rtol": w.rtol, "spheres": w.n_spheres,
+                   "precision": "fp64", "fused_sweeps_per_pass": args.fuse},
+        "cycles": st.cycles,
+        "final_rel_res": st.rel_res,
+        "roofline": roofline,
+    }
+
+    if not args.no_ir:
+        s32 = make_solver(w, dev, precision=pkg.FP32_IR, fuse=args.fuse, inner=args.inner)
+        phi32 = s32.zeros()
+        run_steps(s32, sph_dev, f, phi32, w, args.warmup)
+        t32, wall32, st32 = timed(s32, sph_dev, f, phi32, w, args.steps)
+        _, rel64 = s.residual(phi32, f, want_field=False)
+        diff = (phi32 - phi).abs().max().item()
+        out["fp32_ir"] = {"value": w.cells * args.steps / t32, "ms_per_step": t32 / args.steps * 1e3,
+                          "speedup_vs_fp64": t_gpu / t32, "outer_steps": st32.cycles,
+                          "inner_fp32_cycles": st32.inner_cycles, "final_rel_res_fp64": rel64,
+                          "max_abs_diff_vs_fp64_solution": diff}
+        log(f"fp32-ir: {t32 / args.steps * 1e3:.3f} ms/step, {st32.cycles} outer, rel {rel64:.2e}, "
+            f"max|dphi| vs fp64 {diff:.2e}")
+        del s32, phi32
+
+    if not args.no_cpu:
+        base, phi_cpu = cpu_baseline(w, sph)
+        base["max_abs_diff_gpu_vs_oracle"] = float(np.abs(phi.cpu().numpy() - phi_cpu).max())
+        out["cpu_baseline"] = base
+        log(f"cpu oracle: {base['seconds_per_solve']:.2f} s/solve on {base['cores']} threads")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -78,6 +78,8 @@ typedef struct {
     double cg_rtol;       /* coarsest-grid CG: stop at ||r|| <= cg_rtol ||b|| (default 1e-13) */
     int cg_maxit;         /* coarsest-grid CG iteration cap (0 = 2 x coarsest cells) */
     int fuse_sweeps;      /* RB-GS sweeps fused per smoother kernel pass: 1 or 2 (default 2); iterates are identical */
+    int bottom_cells;     /* the coarse levels from the first one with at most this many cells down to the
+                             coarsest run in one workgroup, in LDS (default 4096, the maximum; 0 = off) */
 } ccmg_options;
 
 typedef struct {
@@ -165,6 +167,18 @@ int ccmg_smooth(ccmg_solver* s, double* d_phi, const double* d_f, int sweeps);
 /* Relative residuals rho_0..rho_k of the last solve (k = cycles); copies at
  * most `max` values into host memory and returns how many it copied. */
 int ccmg_history(const ccmg_solver* s, double* out, int max);
+
+/* Kernel timing for measurement: with profiling on, every finest-level
+ * smoother pass of a cycle is bracketed by HIP events on the solver's stream.
+ * `which` selects the pass by its position in the finest level's pass list of
+ * a cycle (0 = first pre-smoothing pass; with the default V(2,2) and two
+ * sweeps fused per pass: 0 = pre-smoothing + residual + restriction,
+ * 1 = prolongation + post-smoothing + residual norm).  Only cycles that ran
+ * (not those skipped after convergence) are counted.  ccmg_profile_read
+ * returns the summed milliseconds and the launch count, then clears them if
+ * reset != 0.  Timing adds two event records per pass. */
+int ccmg_profile_enable(ccmg_solver* s, int on);
+int ccmg_profile_read(ccmg_solver* s, int which, double* total_ms, int* launches, int reset);
 
 /* Message of the last error on this solver ("" if none); s may be NULL for
  * errors of ccmg_create. */

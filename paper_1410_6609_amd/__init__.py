@@ -48,7 +48,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("levels", ctypes.c_int),
                 ("omega", ctypes.c_double), ("precision", ctypes.c_int),
                 ("ir_inner_cycles", ctypes.c_int), ("cg_rtol", ctypes.c_double),
-                ("cg_maxit", ctypes.c_int), ("fuse_sweeps", ctypes.c_int)]
+                ("cg_maxit", ctypes.c_int), ("fuse_sweeps", ctypes.c_int), ("bottom_cells", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -68,10 +68,12 @@ class Options:
     cg_rtol: float = 1e-13
     cg_maxit: int = 0
     fuse_sweeps: int = 2
+    bottom_cells: int = 4096
 
     def _c(self) -> _Options:
         return _Options(self.nu1, self.nu2, self.levels, self.omega, self.precision,
-                        self.ir_inner_cycles, self.cg_rtol, self.cg_maxit, self.fuse_sweeps)
+                        self.ir_inner_cycles, self.cg_rtol, self.cg_maxit, self.fuse_sweeps,
+                        self.bottom_cells)
 
 
 @dataclass
@@ -104,6 +106,9 @@ _SIGS = {
     "ccmg_residual": ([_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ccmg_smooth": ([_VP, _VP, _VP, ctypes.c_int], ctypes.c_int),
     "ccmg_history": ([_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
+    "ccmg_profile_enable": ([_VP, ctypes.c_int], ctypes.c_int),
+    "ccmg_profile_read": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                           ctypes.c_int], ctypes.c_int),
     "ccmg_last_error": ([_VP], ctypes.c_char_p),
     "ccmg_destroy": ([_VP], None),
 }
@@ -288,6 +293,15 @@ class Solver:
         self._bind_stream()
         self._check(lib().ccmg_smooth(self._h, _ptr(phi), _ptr(f), int(sweeps)))
         return phi
+
+    def profile(self, on: bool = True) -> None:
+        self._check(lib().ccmg_profile_enable(self._h, int(on)))
+
+    def profile_read(self, which: int, reset: bool = True) -> Tuple[float, int]:
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int(0)
+        self._check(lib().ccmg_profile_read(self._h, which, ctypes.byref(ms), ctypes.byref(n), int(reset)))
+        return ms.value, n.value
 
     def history(self):
         buf = (ctypes.c_double * (MAX_CYCLES + 1))()

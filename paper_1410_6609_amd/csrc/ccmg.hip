@@ -30,10 +30,16 @@ using namespace ccmg;
 
 namespace {
 
-// tile shape of the smoother pass: 64 lanes along x, M rows per thread, WY waves
-constexpr int kM = 4;
-constexpr int kWY = 8;
-constexpr int kTargetBlocks = 1024;
+// tile shape of the smoother pass: 64 cells along x (32 lanes x 2), M rows per
+// thread, two row strips per wave, WY waves
+#ifndef CCMG_ROWS
+#define CCMG_ROWS 2
+#endif
+#ifndef CCMG_WAVES
+#define CCMG_WAVES 8
+#endif
+constexpr int kM = CCMG_ROWS;
+constexpr int kWY = CCMG_WAVES;
 
 struct LevelBuf {
     int nx = 0, ny = 0, nz = 0;
@@ -53,20 +59,41 @@ struct Grid {
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// tile-and-chunk decomposition of one pass over an nx*ny*nz level
-Grid pass_grid(int nx, int ny, int nz, int tx, int ty)
+// Tile-and-chunk decomposition of one pass with S stages over an nx*ny*nz
+// level.  A block owning zc planes marches zc + 2S steps (the z halo costs 2S),
+// and blocks run in rounds of `capacity` (CUs x resident blocks per CU).  The
+// chunking minimises rounds x (zc + 2S): long chunks on large levels, short
+// ones (more blocks, fewer sequential steps) on small, latency-bound levels.
+Grid pass_grid(int nx, int ny, int nz, int tx, int ty, int S, int capacity)
 {
     Grid g;
     g.tiles_x = cdiv(nx, tx);
     g.tiles_y = cdiv(ny, ty);
     const int xy = g.tiles_x * g.tiles_y;
-    int chunks = std::max(1, kTargetBlocks / xy);
-    int zc = cdiv(nz, chunks);
-    zc = std::max(8, zc + (zc & 1));      // even, and long enough to amortise the z halo
-    zc = std::min(zc, nz + (nz & 1));
-    g.zc = zc;
-    g.zchunks = cdiv(nz, zc);
+    long best = -1;
+    int best_zc = nz + (nz & 1);
+    for (int chunks = 1; chunks <= (nz + 1) / 2; ++chunks) {
+        int zc = cdiv(nz, chunks);
+        zc += zc & 1;
+        const int nch = cdiv(nz, zc);
+        if (nch != chunks) continue;   // same zc as a smaller chunk count
+        const long blocks = (long)xy * nch;
+        const long rounds = (blocks + capacity - 1) / capacity;
+        const long cost = rounds * (zc + 2 * S);
+        if (best < 0 || cost < best) { best = cost; best_zc = zc; }
+    }
+    g.zc = best_zc;
+    g.zchunks = cdiv(nz, best_zc);
     return g;
+}
+
+// Upper bound of the blocks of any pass over a level: the largest halo
+// (S = 5 stages: two fused sweeps and a residual stage, H = 6) gives the
+// smallest tiles, and chunks hold at least two planes.
+constexpr int kMaxHalo = 6;
+int max_pass_blocks(int nx, int ny, int nz)
+{
+    return cdiv(nx, 64 - 2 * kMaxHalo) * cdiv(ny, 2 * CCMG_WAVES * CCMG_ROWS - 2 * kMaxHalo) * cdiv(nz, 2);
 }
 
 }  // namespace
@@ -81,6 +108,7 @@ struct ccmg_solver {
     int L = 0;
     LevelBuf lv[CCMG_MAX_LEVELS];
     int cg_maxit = 0;
+    int lb = -1;   // first level of the single-workgroup bottom, or -1
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -88,6 +116,13 @@ struct ccmg_solver {
     Ctl* ctl = nullptr;
     double* partials = nullptr;
     int max_partials = 0;
+    // kernel timing (ccmg_profile_*)
+    bool prof = false;
+    struct ProfRec { int cycle, which; hipEvent_t a, b; };
+    std::vector<ProfRec> prof_recs;
+    std::vector<hipEvent_t> prof_pool;
+    double prof_ms[8] = {0};
+    int prof_n[8] = {0};
     // host mirrors
     std::vector<double> hist;
     int last_cycles = 0;
@@ -138,27 +173,35 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // pass dispatch: only the (stages, load, residual) combinations the driver
 // uses are instantiated
 // ---------------------------------------------------------------------------
+int g_num_cus = 256;   // set from the device at workspace attachment
+constexpr size_t kBottomMaxLds = 160 * 1024;
+
 template <typename T, int SPHI, int LOAD, int RES>
-void launch_one(const PassParams<T>& P0, hipStream_t st)
+bool launch_one(const PassParams<T>& P0, hipStream_t st)
 {
     using Sh = PassShape<T, SPHI, RES, kM, kWY>;
+    auto kern = k_pass<T, SPHI, LOAD, RES, kM, kWY>;
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kern), 64 * kWY, 0) !=
+                hipSuccess || nb < 1) {
+            (void)hipGetLastError();
+            nb = 1;
+        }
+        per_cu = nb;
+    }
+    static_assert(Sh::H <= kMaxHalo, "halo larger than the partials bound assumes");
     PassParams<T> P = P0;
-    const Grid g = pass_grid(P.nx, P.ny, P.nz, Sh::TX, Sh::TY);
+    const Grid g = pass_grid(P.nx, P.ny, P.nz, Sh::TX, Sh::TY, Sh::S, g_num_cus * per_cu);
     P.tiles_x = g.tiles_x;
     P.tiles_y = g.tiles_y;
     P.zchunks = g.zchunks;
     P.zc = g.zc;
-    hipLaunchKernelGGL((k_pass<T, SPHI, LOAD, RES, kM, kWY>), dim3(g.blocks()), dim3(64 * kWY), 0, st, P);
-}
-
-template <typename T>
-int pass_blocks(int sphi, int res, int nx, int ny, int nz)
-{
-    auto blocks = [&](int S) {
-        const int H = (S + 1) & ~1;
-        return pass_grid(nx, ny, nz, 64 - 2 * H, kM * kWY - 2 * H).blocks();
-    };
-    return blocks(sphi + (res != RES_NONE ? 1 : 0));
+    // the norm reduction stores one partial per block
+    if ((RES == RES_NORM || RES == RES_NORM_R32 || RES == RES_STORE) && g.blocks() > P.max_partials) return false;
+    hipLaunchKernelGGL(kern, dim3(g.blocks()), dim3(64 * kWY), 0, st, P);
+    return true;
 }
 
 template <typename T, int SPHI>
@@ -167,22 +210,22 @@ bool dispatch_sphi(int load, int res, const PassParams<T>& P, hipStream_t st)
     switch (load) {
     case LOAD_PHI:
         switch (res) {
-        case RES_NONE: launch_one<T, SPHI, LOAD_PHI, RES_NONE>(P, st); return true;
-        case RES_RESTRICT: launch_one<T, SPHI, LOAD_PHI, RES_RESTRICT>(P, st); return true;
-        case RES_NORM: launch_one<T, SPHI, LOAD_PHI, RES_NORM>(P, st); return true;
+        case RES_NONE: return launch_one<T, SPHI, LOAD_PHI, RES_NONE>(P, st);
+        case RES_RESTRICT: return launch_one<T, SPHI, LOAD_PHI, RES_RESTRICT>(P, st);
+        case RES_NORM: return launch_one<T, SPHI, LOAD_PHI, RES_NORM>(P, st);
         default: return false;
         }
     case LOAD_ZERO:
         switch (res) {
-        case RES_NONE: launch_one<T, SPHI, LOAD_ZERO, RES_NONE>(P, st); return true;
-        case RES_RESTRICT: launch_one<T, SPHI, LOAD_ZERO, RES_RESTRICT>(P, st); return true;
+        case RES_NONE: return launch_one<T, SPHI, LOAD_ZERO, RES_NONE>(P, st);
+        case RES_RESTRICT: return launch_one<T, SPHI, LOAD_ZERO, RES_RESTRICT>(P, st);
         default: return false;
         }
     case LOAD_PROLONG:
         switch (res) {
-        case RES_NONE: launch_one<T, SPHI, LOAD_PROLONG, RES_NONE>(P, st); return true;
-        case RES_RESTRICT: launch_one<T, SPHI, LOAD_PROLONG, RES_RESTRICT>(P, st); return true;
-        case RES_NORM: launch_one<T, SPHI, LOAD_PROLONG, RES_NORM>(P, st); return true;
+        case RES_NONE: return launch_one<T, SPHI, LOAD_PROLONG, RES_NONE>(P, st);
+        case RES_RESTRICT: return launch_one<T, SPHI, LOAD_PROLONG, RES_RESTRICT>(P, st);
+        case RES_NORM: return launch_one<T, SPHI, LOAD_PROLONG, RES_NORM>(P, st);
         default: return false;
         }
     default: return false;
@@ -196,10 +239,10 @@ template <>
 bool dispatch<double>(int sphi, int load, int res, const PassParams<double>& P, hipStream_t st)
 {
     if (sphi == 0) {
-        if (load == LOAD_PHI && res == RES_NORM) { launch_one<double, 0, LOAD_PHI, RES_NORM>(P, st); return true; }
-        if (load == LOAD_PHI && res == RES_STORE) { launch_one<double, 0, LOAD_PHI, RES_STORE>(P, st); return true; }
-        if (load == LOAD_PHI && res == RES_NORM_R32) { launch_one<double, 0, LOAD_PHI, RES_NORM_R32>(P, st); return true; }
-        if (load == LOAD_CORR && res == RES_NORM_R32) { launch_one<double, 0, LOAD_CORR, RES_NORM_R32>(P, st); return true; }
+        if (load == LOAD_PHI && res == RES_NORM) { return launch_one<double, 0, LOAD_PHI, RES_NORM>(P, st); }
+        if (load == LOAD_PHI && res == RES_STORE) { return launch_one<double, 0, LOAD_PHI, RES_STORE>(P, st); }
+        if (load == LOAD_PHI && res == RES_NORM_R32) { return launch_one<double, 0, LOAD_PHI, RES_NORM_R32>(P, st); }
+        if (load == LOAD_CORR && res == RES_NORM_R32) { return launch_one<double, 0, LOAD_CORR, RES_NORM_R32>(P, st); }
         return false;
     }
     if (sphi == 2) return dispatch_sphi<double, 2>(load, res, P, st);
@@ -221,6 +264,12 @@ void launch_cg(const T* b, T* x, int nx, int ny, int nz, const int* sh, double r
                hipStream_t st)
 {
     const int n = nx * ny * nz;
+    if (n <= kCgWaveMax) {
+        const size_t lds = (size_t)(nx + 2) * (ny + 2) * (nz + 2) * sizeof(double);
+        hipLaunchKernelGGL((k_coarse_cg_wave<T>), dim3(1), dim3(64), lds, st, b, x, nx, ny, nz, sh[0], sh[1], sh[2],
+                           sh[3], sh[4], sh[5], rtol, maxit, ctl);
+        return;
+    }
     const int npt = cdiv(n, kCgThreads);
 #define CG_CASE(N)                                                                                          \
     hipLaunchKernelGGL((k_coarse_cg<T, N>), dim3(1), dim3(kCgThreads), 0, st, b, x, nx, ny, nz, sh[0], sh[1], \
@@ -298,8 +347,49 @@ PassParams<T> base_params(const ccmg_solver* s, int l)
     for (int f = 0; f < 6; ++f) P.sh[f] = s->sh[f];
     P.ctl = s->ctl;
     P.partials = s->partials;
+    P.max_partials = s->max_partials;
     P.omega = (T)s->opt.omega;
     return P;
+}
+
+// Event bracketing of finest-level passes (only for FP64 cycles that report a
+// norm, i.e. cycles of a solve).  Returns the record index or -1.
+int prof_begin(ccmg_solver* s, int l, int cycle, int which)
+{
+    if (!s->prof || l != 0 || cycle <= 0 || which >= 8) return -1;
+    hipEvent_t ev[2];
+    for (int i = 0; i < 2; ++i) {
+        if (s->prof_pool.empty()) {
+            if (hipEventCreate(&ev[i]) != hipSuccess) return -1;
+        } else {
+            ev[i] = s->prof_pool.back();
+            s->prof_pool.pop_back();
+        }
+    }
+    if (hipEventRecord(ev[0], s->stream) != hipSuccess) return -1;
+    s->prof_recs.push_back({cycle, which, ev[0], ev[1]});
+    return (int)s->prof_recs.size() - 1;
+}
+
+void prof_end(ccmg_solver* s, int idx)
+{
+    if (idx < 0) return;
+    (void)hipEventRecord(s->prof_recs[idx].b, s->stream);
+}
+
+// After a synchronised solve: accumulate the passes of cycles 1..cycles.
+void prof_collect(ccmg_solver* s, int cycles)
+{
+    for (auto& r : s->prof_recs) {
+        float ms = 0.f;
+        if (r.cycle <= cycles && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            s->prof_ms[r.which] += ms;
+            s->prof_n[r.which] += 1;
+        }
+        s->prof_pool.push_back(r.a);
+        s->prof_pool.push_back(r.b);
+    }
+    s->prof_recs.clear();
 }
 
 // Enqueue one V-cycle over levels l0..L-1 of the hierarchy `H` (type T).
@@ -315,7 +405,9 @@ int enqueue_vcycle(ccmg_solver* s, const LevelPtrs<T>& H, bool l0_zero, int fin_
     // descend
     struct Pending { std::vector<PassSpec> ps; std::vector<int> dh; bool copy; size_t next; };
     Pending pend[CCMG_MAX_LEVELS];
-    for (int l = 0; l < L - 1; ++l) {
+    // levels [lbot, L) are handled by the single-workgroup bottom kernel (if any)
+    const int lbot = s->lb > 0 ? s->lb : L - 1;
+    for (int l = 0; l < lbot; ++l) {
         const bool zero = (l > 0) || l0_zero;
         const int post_res = (l == 0 && fin_cycle > 0) ? RES_NORM : RES_NONE;
         pend[l].ps = level_passes(s->opt.nu1, s->opt.nu2, fuse, zero, post_res);
@@ -331,20 +423,47 @@ int enqueue_vcycle(ccmg_solver* s, const LevelPtrs<T>& H, bool l0_zero, int fin_
             P.b = H.b[l];
             P.phi_out = pend[l].dh[i] ? H.home[l] : H.tmp[l];
             P.bc_out = H.b[l + 1];
+            const int pi = prof_begin(s, l, fin_cycle, (int)i);
             if (!dispatch<T>(p.sphi, p.load, p.res, P, st))
                 return fail(s, CCMG_E_ARG, "unsupported smoother pass (%d,%d,%d)", p.sphi, p.load, p.res);
+            prof_end(s, pi);
             cur = P.phi_out;
             pend[l].next = i + 1;
         }
     }
-    // coarsest level
-    {
+    if (lbot < L - 1) {
+        BottomParams<T> B;
+        std::memset(&B, 0, sizeof B);
+        B.b_in = H.b[lbot];
+        B.phi_out = H.home[lbot];
+        B.nlev = L - lbot;
+        for (int i = 0; i < B.nlev; ++i) {
+            B.nx[i] = s->lv[lbot + i].nx;
+            B.ny[i] = s->lv[lbot + i].ny;
+            B.nz[i] = s->lv[lbot + i].nz;
+        }
+        for (int f = 0; f < 6; ++f) B.sh[f] = s->sh[f];
+        B.omega = (T)s->opt.omega;
+        B.nu1 = s->opt.nu1;
+        B.nu2 = s->opt.nu2;
+        B.cg_rtol = s->opt.cg_rtol;
+        B.cg_maxit = s->cg_maxit;
+        B.ctl = s->ctl;
+        int nphi = 0, nb = 0;
+        bottom_layout(B, nphi, nb);
+        const int lc = B.nlev - 1;
+        const size_t npl = (size_t)(B.nx[lc] + 2) * (B.ny[lc] + 2) * (B.nz[lc] + 2);
+        const size_t lds = (((size_t)(nphi + nb) * sizeof(T) + 7) & ~(size_t)7) + npl * sizeof(double);
+        if (lds > kBottomMaxLds) return fail(s, CCMG_E_ARG, "internal: bottom levels need %zu bytes of LDS", lds);
+        hipLaunchKernelGGL((k_bottom<T>), dim3(1), dim3(kBottomThreads), lds, st, B);
+    } else {
+        // coarsest level alone
         const int l = L - 1;
         const LevelBuf& B = s->lv[l];
         launch_cg<T>(H.b[l], H.home[l], B.nx, B.ny, B.nz, s->sh, s->opt.cg_rtol, s->cg_maxit, s->ctl, st);
     }
     // ascend
-    for (int l = L - 2; l >= 0; --l) {
+    for (int l = lbot - 1; l >= 0; --l) {
         Pending& pd = pend[l];
         T* cur = (pd.next > 0) ? (pd.dh[pd.next - 1] ? H.home[l] : H.tmp[l]) : H.home[l];
         for (size_t i = pd.next; i < pd.ps.size(); ++i) {
@@ -358,8 +477,10 @@ int enqueue_vcycle(ccmg_solver* s, const LevelPtrs<T>& H, bool l0_zero, int fin_
                 P.fin = FIN_CYCLE;
                 P.cycle = fin_cycle;
             }
+            const int pi = prof_begin(s, l, fin_cycle, (int)i);
             if (!dispatch<T>(p.sphi, p.load, p.res, P, st))
                 return fail(s, CCMG_E_ARG, "unsupported smoother pass (%d,%d,%d)", p.sphi, p.load, p.res);
+            prof_end(s, pi);
             cur = P.phi_out;
         }
         if (pd.copy) {
@@ -491,6 +612,7 @@ int finish_stats(ccmg_solver* s, const CtlHead& h, int inner_per_step, ccmg_stat
 {
     int rc = read_ctl(s, const_cast<CtlHead&>(h), h.cycles);
     if (rc) return rc;
+    prof_collect(s, h.cycles);
     s->last_cycles = h.cycles > 0 ? h.cycles : s->last_cycles;
     if (st) {
         st->cycles = h.cycles;
@@ -622,6 +744,7 @@ void ccmg_default_options(ccmg_options* o)
     o->cg_rtol = 1e-13;
     o->cg_maxit = 0;
     o->fuse_sweeps = 2;
+    o->bottom_cells = kBottomMaxCells;
 }
 
 int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_face bc[6],
@@ -641,6 +764,8 @@ int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_
     if (o.fuse_sweeps != 1 && o.fuse_sweeps != 2) return fail(nullptr, CCMG_E_ARG, "fuse_sweeps must be 1 or 2");
     if (!(o.cg_rtol > 0.0) || o.cg_maxit < 0) return fail(nullptr, CCMG_E_ARG, "bad CG options");
     if (!std::isfinite(o.omega)) return fail(nullptr, CCMG_E_ARG, "bad omega");
+    if (o.bottom_cells < 0 || o.bottom_cells > kBottomMaxCells)
+        return fail(nullptr, CCMG_E_ARG, "bottom_cells must be in 0..%d", kBottomMaxCells);
     bool any_dirichlet = false;
     for (int f = 0; f < 6; ++f) {
         if (bc[f].kind != CCMG_DIRICHLET && bc[f].kind != CCMG_NEUMANN) return fail(nullptr, CCMG_E_ARG, "bad face kind");
@@ -680,12 +805,14 @@ int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_
     s->stream = (hipStream_t)hip_stream;
     s->L = L;
     s->cg_maxit = o.cg_maxit > 0 ? o.cg_maxit : (int)(2 * ncoarse);
+    // bottom: first coarse level with <= bottom_cells cells that still has a level below it
+    s->lb = -1;
+    for (int l = 1; l < L - 1; ++l) {
+        const size_t n = (size_t)(nx >> l) * (ny >> l) * (nz >> l);
+        if (n <= (size_t)o.bottom_cells && L - l <= kBottomMaxLevels) { s->lb = l; break; }
+    }
 
-    int maxb = 0;
-    for (int sphi : {0, 2, 4})
-        for (int res : {RES_NONE, RES_NORM})
-            maxb = std::max(maxb, pass_blocks<double>(sphi, res, nx, ny, nz));
-    s->max_partials = maxb;
+    s->max_partials = max_pass_blocks(nx, ny, nz);
     for (int l = 0; l < L; ++l) {
         LevelBuf& B = s->lv[l];
         B.nx = nx >> l; B.ny = ny >> l; B.nz = nz >> l;
@@ -705,6 +832,13 @@ int ccmg_set_workspace(ccmg_solver* s, void* d_ptr, size_t bytes)
     if (((uintptr_t)d_ptr & 255) != 0) return fail(s, CCMG_E_ARG, "workspace must be 256-byte aligned");
     if (bytes < s->need_bytes) return fail(s, CCMG_E_STATE, "workspace of %zu bytes, need %zu", bytes, s->need_bytes);
     NEED_DEV(s, d_ptr, "workspace");
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            g_num_cus = ncu;
+        (void)hipGetLastError();
+    }
     char* base = (char*)d_ptr;
     if (layout_workspace(s, base) != s->need_bytes) return fail(s, CCMG_E_STATE, "internal: workspace layout mismatch");
     s->ws = base;
@@ -922,8 +1056,36 @@ int ccmg_history(const ccmg_solver* s, double* out, int max)
     return n;
 }
 
+int ccmg_profile_enable(ccmg_solver* s, int on)
+{
+    if (!s) return CCMG_E_ARG;
+    s->prof = on != 0;
+    return CCMG_OK;
+}
+
+int ccmg_profile_read(ccmg_solver* s, int which, double* total_ms, int* launches, int reset)
+{
+    if (!s || which < 0 || which >= 8) return CCMG_E_ARG;
+    if (total_ms) *total_ms = s->prof_ms[which];
+    if (launches) *launches = s->prof_n[which];
+    if (reset) {
+        s->prof_ms[which] = 0.0;
+        s->prof_n[which] = 0;
+    }
+    return CCMG_OK;
+}
+
 const char* ccmg_last_error(const ccmg_solver* s) { return s ? s->err.c_str() : g_create_err.c_str(); }
 
-void ccmg_destroy(ccmg_solver* s) { delete s; }
+void ccmg_destroy(ccmg_solver* s)
+{
+    if (!s) return;
+    for (auto& r : s->prof_recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : s->prof_pool) (void)hipEventDestroy(e);
+    delete s;
+}
 
 }  // extern "C"

@@ -17,6 +17,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+// planes of phi and b in flight ahead of the plane being smoothed
+#ifndef CCMG_PREFETCH
+#define CCMG_PREFETCH 2
+#endif
+
 namespace ccmg {
 
 // ---------------------------------------------------------------------------
@@ -61,6 +68,7 @@ struct PassParams {
     T* r_out;            // RES_STORE: residual, scaled by rscale
     T rscale;            // RES_STORE
     double* partials;    // RES_NORM*: 2 doubles per block
+    int max_partials;    // capacity of `partials` in blocks (checked on the host)
     Ctl* ctl;            // nullable
     int fin;             // Fin code for the last block
     int cycle;           // FIN_CYCLE: cycle index
@@ -141,46 +149,100 @@ __device__ void finish_norm(double s_r2, double s_b2, double* partials, Ctl* ctl
     const double rn = sqrt(r2), bn = sqrt(b2);
     ctl->counter = 0u;
     ctl->rnorm = rn;
+    // a NaN/Inf anywhere in b or the residual makes one of the sums non-finite
+    const bool finite = isfinite(rn) && isfinite(bn);
+    const double rel = !finite ? (double)NAN : (bn > 0.0 ? rn / bn : 0.0);
     if (fin == FIN_INIT) {
         ctl->bnorm = bn;
-        const double rel = bn > 0.0 ? rn / bn : 0.0;
         ctl->rel = rel;
         ctl->hist[0] = rel;
         ctl->cycles = 0;
-        ctl->bzero = (bn == 0.0);
-        const bool finite = isfinite(rel);
+        ctl->bzero = finite && (bn == 0.0);
         ctl->status = finite ? 0 : -5;
-        ctl->done = (bn == 0.0) || !(rel >= ctl->rtol);
-        ctl->sig_next = rn > 0.0 ? pow2_floor(rn) : 1.0;
+        ctl->done = !finite || (bn == 0.0) || !(rel >= ctl->rtol);
+        ctl->sig_next = (finite && rn > 0.0) ? pow2_floor(rn) : 1.0;
     } else if (fin == FIN_CYCLE) {
-        const double rel = bn > 0.0 ? rn / bn : 0.0;
         ctl->rel = rel;
         if (cycle < kMaxHist) ctl->hist[cycle] = rel;
         ctl->cycles = cycle;
-        const bool finite = isfinite(rel);
         if (!finite) ctl->status = -5;
-        if (!(rel >= ctl->rtol)) ctl->done = 1;
+        if (!finite || !(rel >= ctl->rtol)) ctl->done = 1;
         ctl->sig_cur = ctl->sig_next;
-        ctl->sig_next = rn > 0.0 ? pow2_floor(rn) : 1.0;
+        ctl->sig_next = (finite && rn > 0.0) ? pow2_floor(rn) : 1.0;
     } else if (fin == FIN_STORE) {
         ctl->bnorm = bn;
-        ctl->rel = bn > 0.0 ? rn / bn : 0.0;
+        ctl->rel = rel;
+        ctl->status = finite ? 0 : -5;
     }
 }
 
 // ---------------------------------------------------------------------------
+// Cross-lane moves without LDS: DPP wave shifts by one lane.
+// lane_prev(v): the value v of lane-1; lane_next(v): the value of lane+1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double lane_prev(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_next(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_prev(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_next(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// an x-pair of cells as one vector access (x even, so 2*sizeof(T)-aligned)
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+template <typename T>
+__device__ __forceinline__ void load2(const T* p, T& a, T& b)
+{
+    const typename Vec2<T>::type v = *reinterpret_cast<const typename Vec2<T>::type*>(p);
+    a = v.x;
+    b = v.y;
+}
+template <typename T>
+__device__ __forceinline__ void store2(T* p, T a, T b)
+{
+    typename Vec2<T>::type v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<typename Vec2<T>::type*>(p) = v;
+}
+
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+constexpr int lcm_c(int a, int b) { return a / gcd_c(a, b) * b; }
+
+// ---------------------------------------------------------------------------
 // The smoother pass.
 //
-// One workgroup owns an x-y tile and marches up a chunk of z-planes.  Lanes
-// run along x (coalesced rows), each thread holds M consecutive y-rows, WY
-// waves stack in y.  A pass applies SPHI red-black colour half-sweeps (SPHI/2
-// full sweeps) and optionally a residual stage, all in one read of phi and b:
-// stage s at plane p runs at step t = p + s, so every stage finds the planes
-// p-1, p, p+1 it needs in the per-thread register ring.  The x-neighbours come
-// from the adjacent lanes, y-neighbours from the thread's own rows or, at the
-// edges of its row strip, from LDS (double-buffered per step, one barrier per
-// step).  Each stage is exact on a tile that shrinks by one cell per stage, so
-// the tile carries an H-cell halo that is loaded but not written.
+// One workgroup owns an x-y tile and marches up a chunk of z-planes.  A lane
+// holds an x-pair of cells (x even, x+1): one of each colour, so every
+// red-black half-sweep updates exactly one cell of the pair and which one is
+// known at compile time.  The 64 lanes of a wave form two row groups of 32
+// pairs (64 cells along x, coalesced 16-byte accesses); each thread holds M
+// consecutive rows, and the 2*WY row strips of the workgroup stack in y.
+//
+// A pass applies SPHI colour half-sweeps (SPHI/2 full sweeps, red first,
+// Sec. 5.3) and optionally a residual stage, reading phi and b once: stage s
+// at plane p runs at step t = p + s, so its planes p-1, p, p+1 are in the
+// per-thread register ring.  x-neighbours come from the pair itself or from
+// the adjacent lane (DPP), y-neighbours from the thread's own rows or, at
+// strip edges, from LDS (double-buffered per step: one barrier per step).
+// Each stage is exact on a tile that shrinks by one cell per stage, so the
+// tile carries an H-cell halo that is loaded but never written.
 //
 //   LOAD: phi_in | zero | phi_in + omega * e(parent) | phi_in + sigma * corr
 //   RES:  none | restriction of the residual to the next level's b-tilde |
@@ -190,26 +252,37 @@ template <typename T, int SPHI, int RES, int M, int WY>
 struct PassShape {
     static constexpr int S = SPHI + (RES != RES_NONE ? 1 : 0);   // stages after the load
     static constexpr int H = (S + 1) & ~1;                           // halo, even (restriction pairs)
-    static constexpr int EX = 64;
-    static constexpr int EY = M * WY;
+    static constexpr int EX = 64;                                    // 32 lanes x 2 cells
+    static constexpr int NSTRIP = 2 * WY;
+    static constexpr int EY = NSTRIP * M;
     static constexpr int TX = EX - 2 * H;
     static constexpr int TY = EY - 2 * H;
-    static constexpr int R = S + 2;                                  // ring planes
+    static constexpr int RP = S + 2;                                 // phi ring planes
+    static constexpr int RB = S >= 4 ? RP : S + 1;                   // b ring planes
+    static constexpr int U = lcm_c(lcm_c(lcm_c(RP, RB), 2), CCMG_PREFETCH);   // unrolled steps
     static constexpr int NT = 64 * WY;
-    static constexpr int LDS_STAGES = S > 0 ? S : 1;
+    static constexpr int E1 = SPHI > 0 ? SPHI : 1;                   // single-value edge stages
 };
 
+#ifndef CCMG_PASS_WAVES_PER_EU
+#define CCMG_PASS_WAVES_PER_EU 1
+#endif
+
 template <typename T, int SPHI, int LOAD, int RES, int M, int WY>
-__global__ __launch_bounds__(64 * WY) void k_pass(PassParams<T> P)
+__global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassParams<T> P)
 {
     using Sh = PassShape<T, SPHI, RES, M, WY>;
-    constexpr int S = Sh::S, H = Sh::H, TX = Sh::TX, TY = Sh::TY, R = Sh::R;
+    constexpr int S = Sh::S, H = Sh::H, TX = Sh::TX, TY = Sh::TY, RP = Sh::RP, RB = Sh::RB, U = Sh::U;
+    constexpr int NSTRIP = Sh::NSTRIP;
     static_assert(M % 2 == 0, "rows per thread must be even");
     static_assert(TX > 0 && TY > 0, "tile too small for the halo");
 
     if (P.ctl != nullptr && P.ctl->done) return;
 
-    __shared__ T edge[Sh::LDS_STAGES][2][WY][2][64];
+    // strip-edge exchange: [input of stage j+1][step parity][strip][edge row][pair]
+    __shared__ T edge1[Sh::E1][2][NSTRIP][2][32];
+    // both cells of the edge rows, input of the residual stage
+    __shared__ T edge2[RES != RES_NONE ? 2 : 1][NSTRIP][2][32][2];
 
     const int nblk = P.tiles_x * P.tiles_y * P.zchunks;
     const int blk = xcd_block_id(nblk);
@@ -219,43 +292,51 @@ __global__ __launch_bounds__(64 * WY) void k_pass(PassParams<T> P)
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
+    const int xp = lane & 31;
+    const int strip = 2 * w + (lane >> 5);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
-    const int x = bx * TX - H + lane;
-    const int ybase = by * TY - H + w * M;
+    const int xl = bx * TX - H + 2 * xp;             // even: the pair is (xl, xl+1)
+    const int ybase = by * TY - H + strip * M;       // even
     const int z0 = bz * P.zc;
     const int z1 = min(nz, z0 + P.zc);
-    const bool vx = (x >= 0) && (x < nx);
-    const bool xin = (lane >= H) && (lane < H + TX);
+    const bool vx = (xl >= 0) && (xl < nx);          // nx even: both cells or neither
+    const bool xin = (xp >= H / 2) && (xp < H / 2 + TX / 2);
 
-    // per-row geometry: validity, interior membership and 1/d without the z faces
-    int dxy[M];
-    T invd[M];
+    int dxy[M][2];
+    T inv0[M][2];
     bool vrow[M], yin[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         const int y = ybase + r;
         vrow[r] = vx && (y >= 0) && (y < ny);
-        const int ry = w * M + r;
+        const int ry = strip * M + r;
         yin[r] = (ry >= H) && (ry < H + TY);
-        int d = 6;
-        if (x == 0) d += P.sh[0];
-        if (x == nx - 1) d += P.sh[1];
-        if (y == 0) d += P.sh[2];
-        if (y == ny - 1) d += P.sh[3];
-        dxy[r] = d;
-        invd[r] = T(1) / T(d);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int x = xl + c;
+            int d = 6;
+            if (x == 0) d += P.sh[0];
+            if (x == nx - 1) d += P.sh[1];
+            if (y == 0) d += P.sh[2];
+            if (y == ny - 1) d += P.sh[3];
+            dxy[r][c] = d;
+            inv0[r][c] = T(1) / T(d);
+        }
     }
     const int cnx = nx >> 1, cny = ny >> 1;
     const size_t plane = (size_t)nx * ny;
 
-    T ph[R][M];
-    T bb[R][M];
+    T ph[RP][M][2];
+    T bb[RB][M][2];
 #pragma unroll
-    for (int q = 0; q < R; ++q)
+    for (int q = 0; q < RP; ++q)
 #pragma unroll
-        for (int r = 0; r < M; ++r) { ph[q][r] = T(0); bb[q][r] = T(0); }
+        for (int r = 0; r < M; ++r) { ph[q][r][0] = T(0); ph[q][r][1] = T(0); }
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+#pragma unroll
+        for (int r = 0; r < M; ++r) { bb[q][r][0] = T(0); bb[q][r][1] = T(0); }
 
-    // FP32-IR scales
     T sig_cur = T(0);
     double inv_sig_next = 1.0;
     if constexpr (LOAD == LOAD_CORR) sig_cur = (T)P.ctl->sig_cur;
@@ -266,124 +347,182 @@ __global__ __launch_bounds__(64 * WY) void k_pass(PassParams<T> P)
 #pragma unroll
     for (int r = 0; r < M / 2; ++r) racc[r] = T(0);
 
-    // prefetch registers: plane t+1 is loaded while plane t's stages run
-    T nph[M], nbb[M];
-    auto load_plane = [&](int t, T* dph, T* dbb) {
+    // Prefetch: raw loads of planes t+1 .. t+PD are in flight while plane t's
+    // stages run; they are combined (prolongation / correction) only when the
+    // plane enters the ring, so no load is waited for early.
+    constexpr int PD = CCMG_PREFETCH;
+    T nph[PD][M][2], nbb[PD][M][2], nex[PD][M / 2];
+    float ncr[PD][M][2];
+    auto load_plane = [&](int t, int k) {
         const bool zin = (t >= 0) && (t < nz);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
-            T v = T(0), bv = T(0);
+            T v0 = T(0), v1 = T(0), b0 = T(0), b1 = T(0);
+            float c0 = 0.f, c1 = 0.f;
             if (zin && vrow[r]) {
-                const size_t idx = (size_t)t * plane + (size_t)(ybase + r) * nx + x;
-                bv = P.b[idx];
-                if constexpr (LOAD == LOAD_PHI) v = P.phi_in[idx];
-                if constexpr (LOAD == LOAD_PROLONG)
-                    v = P.phi_in[idx] + P.omega * P.ec[((size_t)(t >> 1) * cny + ((ybase + r) >> 1)) * cnx + (x >> 1)];
-                if constexpr (LOAD == LOAD_CORR) v = P.phi_in[idx] + sig_cur * (T)P.corr[idx];
+                const size_t idx = (size_t)t * plane + (size_t)(ybase + r) * nx + xl;
+                load2(P.b + idx, b0, b1);
+                if constexpr (LOAD != LOAD_ZERO) load2(P.phi_in + idx, v0, v1);
+                if constexpr (LOAD == LOAD_CORR) load2(P.corr + idx, c0, c1);
             }
-            dph[r] = v;
-            dbb[r] = bv;
+            nph[k][r][0] = v0; nph[k][r][1] = v1;
+            nbb[k][r][0] = b0; nbb[k][r][1] = b1;
+            if constexpr (LOAD == LOAD_CORR) { ncr[k][r][0] = c0; ncr[k][r][1] = c1; }
+        }
+        if constexpr (LOAD == LOAD_PROLONG) {
+            // rows r and r+1 share their parent row
+#pragma unroll
+            for (int r = 0; r < M; r += 2) {
+                T e = T(0);
+                if (zin && vrow[r]) e = P.ec[((size_t)(t >> 1) * cny + ((ybase + r) >> 1)) * cnx + (xl >> 1)];
+                nex[k][r / 2] = e;
+            }
         }
     };
 
-    const int tbeg = z0 - S, tend = z1 + S;
-    load_plane(tbeg, nph, nbb);
-
-    for (int tb = tbeg; tb < tend; tb += R) {
+    const int tbeg = z0 - S, tend = z1 + S;     // tbeg has the parity of S (z0 is even)
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
+    for (int k = 0; k < PD; ++k) load_plane(tbeg + k, k);
+
+    for (int tb = tbeg; tb < tend; tb += U) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
             const int t = tb + q;
             if (t < tend) {
-                // ---- stage 0: the prefetched plane t enters the ring; prefetch t+1
+                const int par = t & 1;
+                // ---- stage 0: the prefetched plane t enters the rings; plane t+PD is requested
+                {
+                    const int s0 = q % RP, sb0 = q % RB, k = q % PD;
 #pragma unroll
-                for (int r = 0; r < M; ++r) { ph[q][r] = nph[r]; bb[q][r] = nbb[r]; }
-                if (t + 1 < tend) load_plane(t + 1, nph, nbb);
-                if constexpr (S > 0) {
-                    edge[0][t & 1][w][0][lane] = ph[q][0];
-                    edge[0][t & 1][w][1][lane] = ph[q][M - 1];
+                    for (int r = 0; r < M; ++r) {
+                        T v0 = nph[k][r][0], v1 = nph[k][r][1];
+                        if constexpr (LOAD == LOAD_PROLONG) {
+                            v0 += P.omega * nex[k][r / 2];
+                            v1 += P.omega * nex[k][r / 2];
+                        }
+                        if constexpr (LOAD == LOAD_CORR) {
+                            v0 += sig_cur * (T)ncr[k][r][0];
+                            v1 += sig_cur * (T)ncr[k][r][1];
+                        }
+                        ph[s0][r][0] = v0; ph[s0][r][1] = v1;
+                        bb[sb0][r][0] = nbb[k][r][0]; bb[sb0][r][1] = nbb[k][r][1];
+                    }
+                    if (t + PD < tend) load_plane(t + PD, k);
+                    const int ppar = (S + q) & 1;
+                    if constexpr (SPHI > 0) {
+                        const int o0 = (1 + 0 + ppar) & 1, o1 = (1 + (M - 1) + ppar) & 1;
+                        edge1[0][par][strip][0][xp] = ph[s0][0][o0];
+                        edge1[0][par][strip][1][xp] = ph[s0][M - 1][o1];
+                    } else if constexpr (RES != RES_NONE) {
+                        edge2[par][strip][0][xp][0] = ph[s0][0][0];
+                        edge2[par][strip][0][xp][1] = ph[s0][0][1];
+                        edge2[par][strip][1][xp][0] = ph[s0][M - 1][0];
+                        edge2[par][strip][1][xp][1] = ph[s0][M - 1][1];
+                    }
                 }
-                // ---- stages 1..SPHI: colour half-sweeps, red first (Sec. 5.3)
+                // ---- stages 1..SPHI: colour half-sweeps, red ((x+y+z) even) first
 #pragma unroll
                 for (int s = 1; s <= SPHI; ++s) {
                     const int p = t - s;
-                    constexpr int dummy = 0; (void)dummy;
-                    const int sc = (q - s + 2 * R) % R;
-                    const int sm = (q - s - 1 + 2 * R) % R;
-                    const int sp = (q - s + 1 + 2 * R) % R;
-                    const int colour = (s - 1) & 1;
-                    const T* ein = &edge[s - 1][(t - 1) & 1][0][0][0];
-                    const T yme = (w > 0) ? ein[((w - 1) * 2 + 1) * 64 + lane] : T(0);
-                    const T ype = (w < WY - 1) ? ein[((w + 1) * 2 + 0) * 64 + lane] : T(0);
+                    const int sc = (q - s + 2 * U) % RP;
+                    const int sm = (q - s - 1 + 2 * U) % RP;
+                    const int sp = (q - s + 1 + 2 * U) % RP;
+                    const int sb = (q - s + 2 * U) % RB;
+                    const int cs = (s + 1) & 1;
+                    const int ppar = (S + q - s) & 1;
                     const bool pin = (p >= 0) && (p < nz);
                     int dz = 0;
                     if (p == 0) dz += P.sh[4];
                     if (p == nz - 1) dz += P.sh[5];
+                    const T* ein = &edge1[s - 1][par ^ 1][0][0][0];
+                    const T elo = strip > 0 ? ein[((strip - 1) * 2 + 1) * 32 + xp] : T(0);
+                    const T ehi = strip < NSTRIP - 1 ? ein[((strip + 1) * 2 + 0) * 32 + xp] : T(0);
+                    auto body = [&](auto zbt) {
+                        constexpr bool ZB = decltype(zbt)::value;
 #pragma unroll
-                    for (int r = 0; r < M; ++r) {
-                        const T c = ph[sc][r];
-                        const T xm = __shfl_up(c, 1);
-                        const T xp = __shfl_down(c, 1);
-                        const T ym = (r > 0) ? ph[sc][r - 1] : yme;
-                        const T yp = (r < M - 1) ? ph[sc][r + 1] : ype;
-                        const T sum = ((((xm + xp) + ym) + yp) + ph[sm][r]) + ph[sp][r];
-                        const T inv = (dz == 0) ? invd[r] : T(1) / T(dxy[r] + dz);
-                        const T nv = (bb[sc][r] + sum) * inv;
-                        const bool upd = pin && vrow[r] && (((x + ybase + r + p) & 1) == colour);
-                        ph[sc][r] = upd ? nv : c;
-                    }
-                    if (s < S) {
-                        edge[s][t & 1][w][0][lane] = ph[sc][0];
-                        edge[s][t & 1][w][1][lane] = ph[sc][M - 1];
+                        for (int r = 0; r < M; ++r) {
+                            const int o = (cs + r + ppar) & 1;
+                            const T c = ph[sc][r][o];
+                            T xm, xq;
+                            if (o == 0) { xm = lane_prev(ph[sc][r][1]); xq = ph[sc][r][1]; }
+                            else        { xm = ph[sc][r][0]; xq = lane_next(ph[sc][r][0]); }
+                            const T ym = r > 0 ? ph[sc][r - 1][o] : elo;
+                            const T yp = r < M - 1 ? ph[sc][r + 1][o] : ehi;
+                            const T sum = ((((xm + xq) + ym) + yp) + ph[sm][r][o]) + ph[sp][r][o];
+                            T inv;
+                            if constexpr (ZB) inv = T(1) / T(dxy[r][o] + dz);
+                            else inv = inv0[r][o];
+                            const T nv = (bb[sb][r][o] + sum) * inv;
+                            ph[sc][r][o] = (pin && vrow[r]) ? nv : c;
+                        }
+                    };
+                    if (dz != 0) body(std::true_type{});
+                    else body(std::false_type{});
+                    if (s < SPHI) {
+                        const int o0 = (cs + 0 + ppar) & 1, o1 = (cs + (M - 1) + ppar) & 1;
+                        edge1[s][par][strip][0][xp] = ph[sc][0][o0];
+                        edge1[s][par][strip][1][xp] = ph[sc][M - 1][o1];
+                    } else if (RES != RES_NONE) {
+                        edge2[par][strip][0][xp][0] = ph[sc][0][0];
+                        edge2[par][strip][0][xp][1] = ph[sc][0][1];
+                        edge2[par][strip][1][xp][0] = ph[sc][M - 1][0];
+                        edge2[par][strip][1][xp][1] = ph[sc][M - 1][1];
                     }
                 }
                 // ---- output of the smoothed plane t - SPHI
                 if (P.phi_out != nullptr) {
                     const int po = t - SPHI;
                     if (po >= z0 && po < z1 && xin) {
-                        const int so = (q - SPHI + 2 * R) % R;
+                        const int so = (q - SPHI + 2 * U) % RP;
 #pragma unroll
                         for (int r = 0; r < M; ++r)
                             if (vrow[r] && yin[r])
-                                P.phi_out[(size_t)po * plane + (size_t)(ybase + r) * nx + x] = ph[so][r];
+                                store2(P.phi_out + (size_t)po * plane + (size_t)(ybase + r) * nx + xl, ph[so][r][0],
+                                       ph[so][r][1]);
                     }
                 }
-                // ---- residual stage at plane t - S
+                // ---- residual stage at plane t - S (both cells of every pair)
                 if constexpr (RES != RES_NONE) {
                     const int p = t - S;
-                    const int sc = (q - S + 2 * R) % R;
-                    const int sm = (q - S - 1 + 2 * R) % R;
-                    const int sp = (q - S + 1 + 2 * R) % R;
-                    const T* ein = &edge[S - 1][(t - 1) & 1][0][0][0];
-                    const T yme = (w > 0) ? ein[((w - 1) * 2 + 1) * 64 + lane] : T(0);
-                    const T ype = (w < WY - 1) ? ein[((w + 1) * 2 + 0) * 64 + lane] : T(0);
+                    const int sc = (q - S + 2 * U) % RP;
+                    const int sm = (q - S - 1 + 2 * U) % RP;
+                    const int sp = (q - S + 1 + 2 * U) % RP;
+                    const int sb = (q - S + 2 * U) % RB;
                     const bool pok = (p >= z0) && (p < z1);
                     int dz = 0;
                     if (p == 0) dz += P.sh[4];
                     if (p == nz - 1) dz += P.sh[5];
-                    T res[M];
+                    T elo[2], ehi[2];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        elo[c] = strip > 0 ? edge2[par ^ 1][strip - 1][1][xp][c] : T(0);
+                        ehi[c] = strip < NSTRIP - 1 ? edge2[par ^ 1][strip + 1][0][xp][c] : T(0);
+                    }
+                    T res[M][2];
 #pragma unroll
                     for (int r = 0; r < M; ++r) {
-                        const T c = ph[sc][r];
-                        const T xm = __shfl_up(c, 1);
-                        const T xp = __shfl_down(c, 1);
-                        const T ym = (r > 0) ? ph[sc][r - 1] : yme;
-                        const T yp = (r < M - 1) ? ph[sc][r + 1] : ype;
-                        const T sum = ((((xm + xp) + ym) + yp) + ph[sm][r]) + ph[sp][r];
-                        res[r] = bb[sc][r] - (T(dxy[r] + dz) * c - sum);
+                        const T xm0 = lane_prev(ph[sc][r][1]);
+                        const T xp1 = lane_next(ph[sc][r][0]);
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const T xm = c == 0 ? xm0 : ph[sc][r][0];
+                            const T xq = c == 0 ? ph[sc][r][1] : xp1;
+                            const T ym = r > 0 ? ph[sc][r - 1][c] : elo[c];
+                            const T yp = r < M - 1 ? ph[sc][r + 1][c] : ehi[c];
+                            const T sum = ((((xm + xq) + ym) + yp) + ph[sm][r][c]) + ph[sp][r][c];
+                            res[r][c] = bb[sb][r][c] - (T(dxy[r][c] + dz) * ph[sc][r][c] - sum);
+                        }
                     }
                     if constexpr (RES == RES_RESTRICT) {
-                        // children pairs: x (adjacent lanes), y (rows r, r+1), z (planes p, p+1)
-                        T rx[M];
-#pragma unroll
-                        for (int r = 0; r < M; ++r) rx[r] = res[r] + __shfl_down(res[r], 1);
-                        const bool writer = pok && xin && ((x & 1) == 0);
+                        // children: the pair (x), rows r, r+1 (y), planes p, p+1 (z)
+                        const bool writer = pok && xin;
 #pragma unroll
                         for (int r = 0; r < M; r += 2) {
-                            const T s4 = rx[r] + rx[r + 1];
+                            const T s4 = (res[r][0] + res[r][1]) + (res[r + 1][0] + res[r + 1][1]);
                             if ((p & 1) == 0) {
                                 racc[r / 2] = s4;
                             } else if (writer && vrow[r] && yin[r]) {
-                                P.bc_out[((size_t)(p >> 1) * cny + ((ybase + r) >> 1)) * cnx + (x >> 1)] =
+                                P.bc_out[((size_t)(p >> 1) * cny + ((ybase + r) >> 1)) * cnx + (xl >> 1)] =
                                     T(0.25) * (racc[r / 2] + s4);
                             }
                         }
@@ -392,12 +531,15 @@ __global__ __launch_bounds__(64 * WY) void k_pass(PassParams<T> P)
 #pragma unroll
                             for (int r = 0; r < M; ++r) {
                                 if (vrow[r] && yin[r]) {
-                                    const double rv = (double)res[r];
-                                    acc_r2 += rv * rv;
-                                    acc_b2 += (double)bb[sc][r] * (double)bb[sc][r];
-                                    const size_t idx = (size_t)p * plane + (size_t)(ybase + r) * nx + x;
-                                    if constexpr (RES == RES_NORM_R32) P.r32_out[idx] = (float)(rv * inv_sig_next);
-                                    if constexpr (RES == RES_STORE) if (P.r_out) P.r_out[idx] = res[r] * P.rscale;
+                                    const double r0 = (double)res[r][0], r1 = (double)res[r][1];
+                                    const double b0 = (double)bb[sb][r][0], b1 = (double)bb[sb][r][1];
+                                    acc_r2 += r0 * r0 + r1 * r1;
+                                    acc_b2 += b0 * b0 + b1 * b1;
+                                    const size_t idx = (size_t)p * plane + (size_t)(ybase + r) * nx + xl;
+                                    if constexpr (RES == RES_NORM_R32)
+                                        store2(P.r32_out + idx, (float)(r0 * inv_sig_next), (float)(r1 * inv_sig_next));
+                                    if constexpr (RES == RES_STORE)
+                                        if (P.r_out) store2(P.r_out + idx, res[r][0] * P.rscale, res[r][1] * P.rscale);
                                 }
                             }
                         }
@@ -514,6 +656,323 @@ __global__ __launch_bounds__(kCgThreads) void k_coarse_cg(const T* b, T* x_out, 
         if (c < n) x_out[c] = (T)xr[k];
     }
     if (tid == 0 && ctl != nullptr) ctl->cg_iters = it;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level building blocks for the single-workgroup bottom of the cycle.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, the same value in every lane; fixed
+// association (deterministic): quads, rows of 16 by rotation, then the four
+// row sums in lane order.
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_d<0x124>(v);  // row_ror:4
+    v += dpp_d<0x128>(v);  // row_ror:8
+    double r[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v), 16 * i);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 16 * i);
+        r[i] = __hiloint2double(hi, lo);
+    }
+    return (r[0] + r[1]) + (r[2] + r[3]);
+}
+
+// Index of cell (i,j,k) in an LDS array with a one-cell zero ghost layer.
+__device__ __forceinline__ int padded(int i, int j, int k, int nx, int ny)
+{
+    return ((k + 1) * (ny + 2) + (j + 1)) * (nx + 2) + (i + 1);
+}
+
+__device__ __forceinline__ int cell_diag(int i, int j, int k, int nx, int ny, int nz, const int* sh)
+{
+    int d = 6;
+    if (i == 0) d += sh[0];
+    if (i == nx - 1) d += sh[1];
+    if (j == 0) d += sh[2];
+    if (j == ny - 1) d += sh[3];
+    if (k == 0) d += sh[4];
+    if (k == nz - 1) d += sh[5];
+    return d;
+}
+
+// Conjugate gradients in FP64 by ONE wave on a level of n <= 512 cells
+// (Sec. 5.3: CG on the coarsest grid).  Solves S x = b from x = 0 until
+// ||r|| <= rtol ||b|| or maxit.  The search direction lives in LDS with a zero
+// ghost layer (pl, (nx+2)(ny+2)(nz+2) doubles, ghosts already zero), so every
+// neighbour read is unconditional; b is read with get_b(c) and x written with
+// put_x(c, value), c the unpadded index.  No workgroup barrier: the wave's own
+// LDS accesses are ordered.
+constexpr int kCgWaveMax = 512;
+
+template <typename GetB, typename PutX>
+__device__ int cg_one_wave(GetB get_b, PutX put_x, double* pl, int nx, int ny, int nz, const int* sh, double rtol,
+                           int maxit)
+{
+    constexpr int NPT = kCgWaveMax / 64;
+    const int lane = threadIdx.x & 63;
+    const int n = nx * ny * nz;
+    const int sy = nx + 2, sz = (nx + 2) * (ny + 2);
+    double xr[NPT], rr_[NPT], qv[NPT];
+    int pc_[NPT], dg[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int c = lane + 64 * k;
+        const bool v = c < n;
+        const int i = v ? c % nx : 0, j = v ? (c / nx) % ny : 0, kk = v ? c / (nx * ny) : 0;
+        dg[k] = v ? cell_diag(i, j, kk, nx, ny, nz, sh) : 0;
+        pc_[k] = padded(i, j, kk, nx, ny);
+        xr[k] = 0.0;
+        rr_[k] = v ? (double)get_b(c) : 0.0;
+        if (v) pl[pc_[k]] = rr_[k];
+    }
+    double loc = 0.0;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) loc += rr_[k] * rr_[k];
+    double rr = wave_sum_dpp(loc);
+    const double bnorm = sqrt(rr);
+    int it = 0;
+    if (bnorm > 0.0) {
+        while (it < maxit) {
+            double pv[NPT];
+            double pq = 0.0;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int c = pc_[k];
+                pv[k] = pl[c];
+                const double s = ((((pl[c - 1] + pl[c + 1]) + pl[c - sy]) + pl[c + sy]) + pl[c - sz]) + pl[c + sz];
+                qv[k] = dg[k] ? (double)dg[k] * pv[k] - s : 0.0;
+                pq += dg[k] ? pv[k] * qv[k] : 0.0;
+            }
+            pq = wave_sum_dpp(pq);
+            const double alpha = rr / pq;
+            double loc2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                if (dg[k]) {
+                    xr[k] += alpha * pv[k];
+                    rr_[k] -= alpha * qv[k];
+                }
+                loc2 += rr_[k] * rr_[k];
+            }
+            const double rr_new = wave_sum_dpp(loc2);
+            ++it;
+            if (sqrt(rr_new) <= rtol * bnorm) break;
+            const double beta = rr_new / rr;
+            rr = rr_new;
+            // every lane has read p (its values are in pv); the wave's stores follow its loads
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < NPT; ++k)
+                if (dg[k]) pl[pc_[k]] = rr_[k] + beta * pv[k];
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int c = lane + 64 * k;
+        if (c < n) put_x(c, xr[k]);
+    }
+    return it;
+}
+
+constexpr int kCgPad = 10 * 10 * 10 + 64;   // padded cells of the largest one-wave grid shapes, with slack
+
+// Standalone coarsest-grid CG for n <= 512 cells: one wave.
+template <typename T>
+__global__ __launch_bounds__(64) void k_coarse_cg_wave(const T* b, T* x_out, int nx, int ny, int nz, int sh0,
+                                                       int sh1, int sh2, int sh3, int sh4, int sh5, double rtol,
+                                                       int maxit, Ctl* ctl)
+{
+    if (ctl != nullptr && ctl->done) return;
+    extern __shared__ double pl[];
+    const int sh[6] = {sh0, sh1, sh2, sh3, sh4, sh5};
+    const int np = (nx + 2) * (ny + 2) * (nz + 2);
+    for (int c = threadIdx.x; c < np; c += 64) pl[c] = 0.0;
+    __syncthreads();
+    const int it = cg_one_wave([&](int c) { return b[c]; }, [&](int c, double v) { x_out[c] = (T)v; }, pl, nx, ny,
+                               nz, sh, rtol, maxit);
+    if (threadIdx.x == 0 && ctl != nullptr) ctl->cg_iters = it;
+}
+
+// ---------------------------------------------------------------------------
+// The bottom of the V-cycle in one workgroup.  Levels lb..L-1, where level lb
+// has at most 4096 cells, live entirely in LDS (phi with a zero ghost layer,
+// b-tilde, the CG direction): one kernel runs the pre-smoothing, residual
+// restriction, coarsest CG (one wave), prolongation with the magnified
+// correction and post-smoothing of all of them (Sec. 3), reading b-tilde of
+// level lb and writing its correction phi (the guess on every coarse level is
+// zero).  It replaces two pass launches per level and the CG launch, whose
+// cost on such small grids is latency, not bandwidth.
+// ---------------------------------------------------------------------------
+constexpr int kBottomThreads = 512;
+constexpr int kBottomMaxCells = 4096;
+constexpr int kBottomMaxLevels = 6;
+constexpr int kBottomCpt = kBottomMaxCells / 2 / kBottomThreads;   // cells of one colour per thread
+
+template <typename T>
+struct BottomParams {
+    const T* b_in;      // b-tilde of level lb (global)
+    T* phi_out;         // phi of level lb (global, its home buffer)
+    int nlev;           // levels in the bottom (>= 2; the last one is solved by CG)
+    int nx[kBottomMaxLevels], ny[kBottomMaxLevels], nz[kBottomMaxLevels];
+    int poff[kBottomMaxLevels];   // offsets of the padded phi arrays
+    int boff[kBottomMaxLevels];   // offsets of the b-tilde arrays
+    int sh[6];
+    T omega;
+    int nu1, nu2;
+    double cg_rtol;
+    int cg_maxit;
+    Ctl* ctl;
+};
+
+// LDS footprint (elements of T) of the padded phi and plain b arrays of a bottom
+template <typename T>
+__host__ __device__ inline void bottom_layout(BottomParams<T>& B, int& nphi, int& nb)
+{
+    nphi = 0;
+    nb = 0;
+    for (int l = 0; l < B.nlev; ++l) {
+        B.poff[l] = nphi;
+        B.boff[l] = nb;
+        nphi += (B.nx[l] + 2) * (B.ny[l] + 2) * (B.nz[l] + 2);
+        nb += B.nx[l] * B.ny[l] * B.nz[l];
+    }
+}
+
+// `sweeps` red-black sweeps on one level in LDS; each thread owns fixed cells
+// of each colour, their padded index and diagonal computed once per call.
+template <typename T>
+__device__ void bottom_smooth(T* ph, const T* bt, int nx, int ny, int nz, const int* sh, int sweeps)
+{
+    const int hx = nx / 2, half = hx * ny * nz;   // nx even: each colour has half the cells
+    const int sy = nx + 2, sz = (nx + 2) * (ny + 2);
+    int pidx[2][kBottomCpt], bidx[2][kBottomCpt], dg[2][kBottomCpt];
+#pragma unroll
+    for (int colour = 0; colour < 2; ++colour)
+#pragma unroll
+        for (int u = 0; u < kBottomCpt; ++u) {
+            const int m = threadIdx.x + u * kBottomThreads;
+            const bool v = m < half;
+            const int ip = v ? m % hx : 0, j = v ? (m / hx) % ny : 0, k = v ? m / (hx * ny) : 0;
+            const int i = 2 * ip + ((j + k + colour) & 1);
+            pidx[colour][u] = padded(i, j, k, nx, ny);
+            bidx[colour][u] = (k * ny + j) * nx + i;
+            dg[colour][u] = v ? cell_diag(i, j, k, nx, ny, nz, sh) : 0;
+        }
+    for (int sw = 0; sw < sweeps; ++sw) {
+#pragma unroll
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma unroll
+            for (int u = 0; u < kBottomCpt; ++u) {
+                if (dg[colour][u] == 0) continue;
+                const int c = pidx[colour][u];
+                const T sum = ((((ph[c - 1] + ph[c + 1]) + ph[c - sy]) + ph[c + sy]) + ph[c - sz]) + ph[c + sz];
+                ph[c] = (bt[bidx[colour][u]] + sum) / T(dg[colour][u]);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomParams<T> P)
+{
+    if (P.ctl != nullptr && P.ctl->done) return;
+    extern __shared__ char lds_raw[];
+    const int lc = P.nlev - 1;
+    // offsets were laid out on the host by bottom_layout
+    const int nphi = P.poff[lc] + (P.nx[lc] + 2) * (P.ny[lc] + 2) * (P.nz[lc] + 2);
+    const int nb = P.boff[lc] + P.nx[lc] * P.ny[lc] * P.nz[lc];
+    T* ph_all = reinterpret_cast<T*>(lds_raw);
+    T* b_all = ph_all + nphi;
+    double* pl = reinterpret_cast<double*>(lds_raw + (((size_t)(nphi + nb) * sizeof(T) + 7) & ~(size_t)7));
+    const int npl = (P.nx[lc] + 2) * (P.ny[lc] + 2) * (P.nz[lc] + 2);
+    // zero every phi (ghosts stay zero) and the CG direction
+    for (int c = threadIdx.x; c < nphi; c += kBottomThreads) ph_all[c] = T(0);
+    for (int c = threadIdx.x; c < npl; c += kBottomThreads) pl[c] = 0.0;
+    const int n0 = P.nx[0] * P.ny[0] * P.nz[0];
+    for (int c = threadIdx.x; c < n0; c += kBottomThreads) b_all[c] = P.b_in[c];
+    __syncthreads();
+    // descend
+    for (int l = 0; l < lc; ++l) {
+        const int nx = P.nx[l], ny = P.ny[l], nz = P.nz[l];
+        T* ph = ph_all + P.poff[l];
+        const T* bt = b_all + P.boff[l];
+        bottom_smooth(ph, bt, nx, ny, nz, P.sh, P.nu1);
+        // b-tilde of level l+1 = 1/4 sum of the children's residuals
+        const int cnx = nx / 2, cny = ny / 2, cnz = nz / 2, nc = cnx * cny * cnz;
+        const int sy = nx + 2, sz = (nx + 2) * (ny + 2);
+        T* bc = b_all + P.boff[l + 1];
+        for (int C = threadIdx.x; C < nc; C += kBottomThreads) {
+            const int I = C % cnx, J = (C / cnx) % cny, K = C / (cnx * cny);
+            T acc[2][2];
+#pragma unroll
+            for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+                for (int dj = 0; dj < 2; ++dj) {
+                    T pair = T(0);
+#pragma unroll
+                    for (int di = 0; di < 2; ++di) {
+                        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+                        const int c = padded(i, j, k, nx, ny);
+                        const T sum =
+                            ((((ph[c - 1] + ph[c + 1]) + ph[c - sy]) + ph[c + sy]) + ph[c - sz]) + ph[c + sz];
+                        const T r = bt[(k * ny + j) * nx + i] - (T(cell_diag(i, j, k, nx, ny, nz, P.sh)) * ph[c] - sum);
+                        pair = di == 0 ? r : pair + r;
+                    }
+                    acc[dk][dj] = pair;
+                }
+            bc[C] = T(0.25) * ((acc[0][0] + acc[0][1]) + (acc[1][0] + acc[1][1]));
+        }
+        __syncthreads();
+    }
+    // coarsest level: CG by wave 0, from the b-tilde in LDS into phi's interior
+    if (threadIdx.x < 64) {
+        const int nx = P.nx[lc], ny = P.ny[lc];
+        const T* bt = b_all + P.boff[lc];
+        T* ph = ph_all + P.poff[lc];
+        const int it = cg_one_wave(
+            [&](int c) { return bt[c]; },
+            [&](int c, double v) {
+                const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+                ph[padded(i, j, k, nx, ny)] = (T)v;
+            },
+            pl, nx, ny, P.nz[lc], P.sh, P.cg_rtol, P.cg_maxit);
+        if (threadIdx.x == 0 && P.ctl != nullptr) P.ctl->cg_iters = it;
+    }
+    __syncthreads();
+    // ascend
+    for (int l = lc - 1; l >= 0; --l) {
+        const int nx = P.nx[l], ny = P.ny[l], nz = P.nz[l], n = nx * ny * nz;
+        const int cnx = nx / 2, cny = ny / 2;
+        T* ph = ph_all + P.poff[l];
+        const T* pc = ph_all + P.poff[l + 1];
+        for (int c = threadIdx.x; c < n; c += kBottomThreads) {
+            const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+            ph[padded(i, j, k, nx, ny)] += P.omega * pc[padded(i >> 1, j >> 1, k >> 1, cnx, cny)];
+        }
+        __syncthreads();
+        bottom_smooth(ph, b_all + P.boff[l], nx, ny, nz, P.sh, P.nu2);
+    }
+    {
+        const int nx = P.nx[0], ny = P.ny[0];
+        const T* ph = ph_all + P.poff[0];
+        for (int c = threadIdx.x; c < n0; c += kBottomThreads) {
+            const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+            P.phi_out[c] = ph[padded(i, j, k, nx, ny)];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

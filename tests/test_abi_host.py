@@ -77,6 +77,7 @@ def test_workspace_size_covers_hierarchy():
     ((32, 32, 32), ZD, dict(fuse_sweeps=3), pkg.E_ARG),
     ((256, 256, 256), ZD, dict(levels=2), pkg.E_DIMS),       # coarsest grid too large for one workgroup
     ((32, 32, 32), ZD, dict(precision=7), pkg.E_ARG),
+    ((32, 32, 32), ZD, dict(bottom_cells=5000), pkg.E_ARG),
     ((32, 32, 32), (0, 0, 0, 0, 0, 5), {}, pkg.E_ARG),
 ])
 def test_create_rejects(shape, kinds, opt, code):
@@ -105,3 +106,4 @@ def test_defaults():
     pkg.lib().ccmg_default_options(ctypes.byref(o))
     assert (o.nu1, o.nu2, o.omega, o.precision, o.levels) == (2, 2, 2.0, 0, 0)
     assert o.cg_rtol == 1e-13
+    assert (o.fuse_sweeps, o.bottom_cells) == (2, 4096)

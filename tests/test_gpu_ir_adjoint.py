@@ -1,0 +1,172 @@
+"""GPU parity of the two extensions: FP32 cycles inside FP64 iterative
+refinement, and the adjoint solve with gradients (dL/df, dL/drho, dL/dq,
+autograd), plus the error paths of the C ABI forced from the host."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1410_6609_amd as pkg
+import workloads as W
+from workloads import DIRICHLET as D, NEUMANN as N
+
+from test_gpu_parity import CASES, DEV, ids, log_case, rhs, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def solver(shape, levels, kinds, values, h=None, **opt):
+    h = 1.0 / shape[0] if h is None else h
+    return pkg.Solver(shape, h, list(zip(kinds, values)), pkg.Options(levels=levels, **opt), device=DEV)
+
+
+@pytest.mark.parametrize("inner", [1, 2, 3])
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_fp32_ir_reaches_fp64_accuracy(case, inner):
+    shape, levels, kinds, values = case
+    log_case("ir", shape, inner)
+    h = 1.0 / shape[0]
+    s = solver(shape, levels, kinds, values, precision=pkg.FP32_IR, ir_inner_cycles=inner)
+    f = rhs(shape, 11)
+    phi, st = s.solve(to_dev(f), rtol=1e-10)
+    assert st.rel_res < 1e-10 and st.inner_cycles == inner * st.cycles
+    got = phi.cpu().numpy()
+    b = oracle.fold(f, h, kinds, values)
+    # the oracle's own FP64 residual of the GPU result
+    rel = oracle.norm2(oracle.residual(got, b, h, kinds)) / oracle.norm2(b)
+    assert rel < 1.0001e-10
+    ref, _, _ = oracle.solve(b, h, kinds, levels, rtol=1e-13)
+    assert np.abs(got - ref).max() <= 1e-7 * np.abs(ref).max()
+    # same refinement algorithm in the oracle (float arithmetic on the CPU)
+    _, ohist, ost = oracle.solve_ir(b, h, kinds, levels, inner=inner, rtol=1e-10)
+    assert ost == 0 and abs((len(ohist) - 1) - st.cycles) <= 1
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=ids)
+def test_adjoint_parity(case):
+    shape, levels, kinds, values = case
+    log_case("adjoint", shape)
+    h = 1.0 / shape[0]
+    s = solver(shape, levels, kinds, values)
+    g = rhs(shape, 12)
+    lam, _, drho, st = s.adjoint(to_dev(g), eps=0.5, want_drho=True, rtol=1e-10)
+    ref, hist, _ = oracle.adjoint(g, h, kinds, levels, rtol=1e-10)
+    assert st.cycles == len(hist) - 1
+    got = lam.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert torch.equal(drho, lam * 2.0)   # dL/drho = lambda / eps with eps = 1/2 (exact)
+
+
+def spheres_case(shape=(64, 64, 64), levels=4, n=24, seed=77, r=(2.5, 4.0)):
+    w = W.Workload("adj", shape, 1.0, (D,) * 6, (0.0,) * 6, levels=levels, n_spheres=n, r_lo=r[0],
+                   r_hi=r[1], seed=seed)
+    return w, W.workload_spheres(w)
+
+
+def test_dq_parity_and_autograd():
+    w, sph = spheres_case()
+    s = solver(w.shape, w.levels, w.kinds, w.values, h=w.h)
+    wts = W.random_field(w.shape, 13)
+    c, r, q = (to_dev(a) for a in (sph.centers, sph.radii, sph.charges))
+    lam, dq, _, st = s.adjoint(to_dev(wts), c, r, eps=1.0, rtol=1e-10)
+    lam_ref, hist, _ = oracle.adjoint(wts, w.h, w.kinds, w.levels, rtol=1e-10)
+    dq_ref = oracle.dq(lam_ref, w.h, sph.centers, sph.radii)
+    assert np.abs(dq.cpu().numpy() - dq_ref).max() <= 1e-11 * np.abs(dq_ref).max()
+    # the same gradient through torch.autograd
+    qg = q.clone().requires_grad_(True)
+    phi = pkg.PoissonFn.apply(qg, c, r, s, 1.0, 1e-10, 100)
+    loss = (phi * to_dev(wts)).sum()
+    loss.backward()
+    assert np.abs(qg.grad.cpu().numpy() - dq_ref).max() <= 1e-11 * np.abs(dq_ref).max()
+    # RhsSolveFn: dL/df = lambda
+    fr = s.deposit(c, r, q).requires_grad_(True)
+    phi2 = pkg.RhsSolveFn.apply(fr, s, 1e-10, 100)
+    (phi2 * to_dev(wts)).sum().backward()
+    assert np.abs(fr.grad.cpu().numpy() - lam_ref).max() <= 1e-12 * np.abs(lam_ref).max()
+
+
+def test_dq_matches_finite_differences_fixed_cycles():
+    """Central differences (step 1e-6) of L = sum w phi over sphere charges, with
+    the forward solves run for a fixed cycle count so that the discrete map
+    q -> phi is linear and smooth (its contraction makes the remainder negligible)."""
+    w = W.C4.scaled((64, 64, 64), levels=4, n_spheres=40)
+    sph = W.workload_spheres(w)
+    s = solver(w.shape, w.levels, w.kinds, w.values, h=w.h)
+    wts = to_dev(W.loss_weights(w))
+    c, r = to_dev(sph.centers), to_dev(sph.radii)
+    idx = W.fd_sphere_indices(w)
+    _, dq, _, _ = s.adjoint(wts, c, r, rtol=1e-13, max_cycles=60)
+    k = 24
+    def loss(qv):
+        f = s.deposit(c, r, to_dev(qv))
+        phi, _ = s.solve(f, rtol=0.0, max_cycles=k, check=False)
+        return float((phi * wts).sum())
+    step = w.extra["fd_step"]
+    dq = dq.cpu().numpy()
+    for i in idx:
+        qp, qm = sph.charges.copy(), sph.charges.copy()
+        qp[i] += step
+        qm[i] -= step
+        fd = (loss(qp) - loss(qm)) / (2 * step)
+        assert abs(fd - dq[i]) <= 1e-6 * max(abs(dq[i]), 1e-3 * np.abs(dq).max()), (i, fd, dq[i])
+
+
+def test_fp32_ir_gradient_matches_fp64():
+    w = W.C4.scaled((128, 128, 128), levels=5, n_spheres=100)
+    sph = W.workload_spheres(w)
+    c, r = to_dev(sph.centers), to_dev(sph.radii)
+    wts = to_dev(W.loss_weights(w))
+    out = {}
+    for prec in (pkg.FP64, pkg.FP32_IR):
+        s = solver(w.shape, w.levels, w.kinds, w.values, h=w.h, precision=prec)
+        _, dq, _, st = s.adjoint(wts, c, r, rtol=1e-10)
+        out[prec] = dq.cpu().numpy()
+    rel = np.abs(out[pkg.FP32_IR] - out[pkg.FP64]).max() / np.abs(out[pkg.FP64]).max()
+    assert rel <= 1e-6
+
+
+# ---- error paths, forced from the host ------------------------------------
+def test_nonfinite_rhs_reports_error():
+    shape, levels, kinds, values = CASES[1]
+    s = solver(shape, levels, kinds, values)
+    f = rhs(shape, 14)
+    f[3, 4, 5] = np.nan
+    phi, st = s.solve(to_dev(f), check=False)
+    assert st.status == pkg.E_NONFINITE
+
+
+def test_max_cycles_reports_noconv():
+    shape, levels, kinds, values = CASES[1]
+    s = solver(shape, levels, kinds, values)
+    phi, st = s.solve(to_dev(rhs(shape, 15)), rtol=1e-10, max_cycles=1, check=False)
+    assert st.status == pkg.E_NOCONV and st.cycles == 1 and st.rel_res > 1e-10
+    with pytest.raises(pkg.CcmgError):
+        s.solve(to_dev(rhs(shape, 15)), rtol=1e-10, max_cycles=1)
+
+
+def test_zero_rhs_gives_zero_solution():
+    shape, levels, kinds, _ = CASES[1]
+    s = solver(shape, levels, kinds, (0.0,) * 6)
+    phi = torch.ones((shape[2], shape[1], shape[0]), dtype=torch.float64, device=DEV)
+    phi, st = s.solve(s.zeros(), phi)
+    assert st.cycles == 0 and not phi.any()
+
+
+def test_host_pointer_rejected():
+    import ctypes
+    shape, levels, kinds, values = CASES[0]
+    s = solver(shape, levels, kinds, values)
+    host = np.zeros((shape[2], shape[1], shape[0]))
+    hp = ctypes.c_void_p(host.ctypes.data)
+    rc = pkg.lib().ccmg_solve(s._h, hp, hp, 1e-10, 10, None)
+    assert rc == pkg.E_ARG
+    assert b"device memory" in pkg.lib().ccmg_last_error(s._h)
+
+
+def test_initial_guess_warm_start():
+    shape, levels, kinds, values = CASES[3]
+    s = solver(shape, levels, kinds, values)
+    f = to_dev(rhs(shape, 16))
+    phi, st = s.solve(f, rtol=1e-11)
+    phi2, st2 = s.solve(f, phi.clone(), rtol=1e-10)
+    assert st2.cycles == 0 and torch.equal(phi2, phi)

@@ -132,6 +132,21 @@ def test_fusion_and_tiling_invariance():
     assert np.array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[4]], ids=ids)
+def test_bottom_kernel_matches_pass_path(case):
+    """The coarse levels run either as smoother passes plus a separate CG launch
+    or inside the single-workgroup bottom kernel: same method, same iterates up
+    to rounding."""
+    shape, levels, kinds, values = case
+    f = to_dev(rhs(shape, 8))
+    out = []
+    for cells in (0, 4096):
+        s = solver_for(shape, levels, kinds, values, bottom_cells=cells)
+        phi, _ = s.solve(f, rtol=0.0, max_cycles=4, check=False)
+        out.append(phi.cpu().numpy())
+    assert np.abs(out[0] - out[1]).max() <= 1e-13 * np.abs(out[0]).max()
+
+
 def test_c1_sine_closed_form():
     w = W.C1
     s = pkg.Solver(w.shape, w.h, list(zip(w.kinds, w.values)), pkg.Options(levels=w.levels), device=DEV)
