@@ -259,7 +259,9 @@ struct PassShape {
     static constexpr int TY = EY - 2 * H;
     static constexpr int RP = S + 2;                                 // phi ring planes
     static constexpr int RB = S >= 4 ? RP : S + 1;                   // b ring planes
-    static constexpr int U = lcm_c(lcm_c(lcm_c(RP, RB), 2), CCMG_PREFETCH);   // unrolled steps
+    // planes in flight: the five-stage passes have no registers to spare for a second one
+    static constexpr int PD = CCMG_PREFETCH;
+    static constexpr int U = lcm_c(lcm_c(lcm_c(RP, RB), 2), PD);   // unrolled steps
     static constexpr int NT = 64 * WY;
     static constexpr int E1 = SPHI > 0 ? SPHI : 1;                   // single-value edge stages
 };
@@ -320,7 +322,8 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
             if (y == 0) d += P.sh[2];
             if (y == ny - 1) d += P.sh[3];
             dxy[r][c] = d;
-            inv0[r][c] = T(1) / T(d);
+            // cells outside the domain get 1/d = 0: their update is exactly 0, no select needed
+            inv0[r][c] = vrow[r] ? T(1) / T(d) : T(0);
         }
     }
     const int cnx = nx >> 1, cny = ny >> 1;
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     // Prefetch: raw loads of planes t+1 .. t+PD are in flight while plane t's
     // stages run; they are combined (prolongation / correction) only when the
     // plane enters the ring, so no load is waited for early.
-    constexpr int PD = CCMG_PREFETCH;
+    constexpr int PD = Sh::PD;
     T nph[PD][M][2], nbb[PD][M][2], nex[PD][M / 2];
     float ncr[PD][M][2];
     auto load_plane = [&](int t, int k) {
@@ -442,7 +445,6 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
 #pragma unroll
                         for (int r = 0; r < M; ++r) {
                             const int o = (cs + r + ppar) & 1;
-                            const T c = ph[sc][r][o];
                             T xm, xq;
                             if (o == 0) { xm = lane_prev(ph[sc][r][1]); xq = ph[sc][r][1]; }
                             else        { xm = ph[sc][r][0]; xq = lane_next(ph[sc][r][0]); }
@@ -450,14 +452,16 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                             const T yp = r < M - 1 ? ph[sc][r + 1][o] : ehi;
                             const T sum = ((((xm + xq) + ym) + yp) + ph[sm][r][o]) + ph[sp][r][o];
                             T inv;
-                            if constexpr (ZB) inv = T(1) / T(dxy[r][o] + dz);
+                            if constexpr (ZB) inv = vrow[r] ? T(1) / T(dxy[r][o] + dz) : T(0);
                             else inv = inv0[r][o];
                             const T nv = (bb[sb][r][o] + sum) * inv;
-                            ph[sc][r][o] = (pin && vrow[r]) ? nv : c;
+                            ph[sc][r][o] = (pin && vrow[r]) ? nv : ph[sc][r][o];
                         }
                     };
                     if (dz != 0) body(std::true_type{});
                     else body(std::false_type{});
+                    // keep the stages apart in the schedule (bounds register live ranges)
+                    __builtin_amdgcn_sched_barrier(0);
                     if (s < SPHI) {
                         const int o0 = (cs + 0 + ppar) & 1, o1 = (cs + (M - 1) + ppar) & 1;
                         edge1[s][par][strip][0][xp] = ph[sc][0][o0];
@@ -706,24 +710,59 @@ __device__ __forceinline__ int cell_diag(int i, int j, int k, int nx, int ny, in
     return d;
 }
 
+// 1/x to full double precision: hardware reciprocal estimate and two Newton
+// steps (each doubles the correct bits); no IEEE division sequence on the
+// critical path of the one-wave CG.
+__device__ __forceinline__ double fast_rcp(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+// Two wave sums at once (independent chains interleave).
+__device__ __forceinline__ void wave_sum2_dpp(double& a, double& b)
+{
+    a += dpp_d<0xB1>(a); b += dpp_d<0xB1>(b);
+    a += dpp_d<0x4E>(a); b += dpp_d<0x4E>(b);
+    a += dpp_d<0x124>(a); b += dpp_d<0x124>(b);
+    a += dpp_d<0x128>(a); b += dpp_d<0x128>(b);
+    double ra[4], rb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        ra[i] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(a), 16 * i),
+                                 __builtin_amdgcn_readlane(__double2loint(a), 16 * i));
+        rb[i] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(b), 16 * i),
+                                 __builtin_amdgcn_readlane(__double2loint(b), 16 * i));
+    }
+    a = (ra[0] + ra[1]) + (ra[2] + ra[3]);
+    b = (rb[0] + rb[1]) + (rb[2] + rb[3]);
+}
+
 // Conjugate gradients in FP64 by ONE wave on a level of n <= 512 cells
 // (Sec. 5.3: CG on the coarsest grid).  Solves S x = b from x = 0 until
-// ||r|| <= rtol ||b|| or maxit.  The search direction lives in LDS with a zero
-// ghost layer (pl, (nx+2)(ny+2)(nz+2) doubles, ghosts already zero), so every
-// neighbour read is unconditional; b is read with get_b(c) and x written with
-// put_x(c, value), c the unpadded index.  No workgroup barrier: the wave's own
-// LDS accesses are ordered.
+// ||r|| <= rtol ||b|| or maxit.  The recurrences are arranged as in
+// Chronopoulos and Gear (1989): the matrix product is taken of the residual,
+// and both inner products of an iteration, (r,r) and (r,S r), come from one
+// combined reduction; in exact arithmetic the iterates are those of standard
+// CG.  The residual lives in LDS with a zero ghost layer (rl,
+// (nx+2)(ny+2)(nz+2) doubles, ghosts already zero), so every neighbour read is
+// unconditional; b is read with get_b(c) and x written with put_x(c, value),
+// c the unpadded index.  No workgroup barrier: the wave's own LDS accesses are
+// ordered.
 constexpr int kCgWaveMax = 512;
 
 template <typename GetB, typename PutX>
-__device__ int cg_one_wave(GetB get_b, PutX put_x, double* pl, int nx, int ny, int nz, const int* sh, double rtol,
+__device__ int cg_one_wave(GetB get_b, PutX put_x, double* rl, int nx, int ny, int nz, const int* sh, double rtol,
                            int maxit)
 {
     constexpr int NPT = kCgWaveMax / 64;
     const int lane = threadIdx.x & 63;
     const int n = nx * ny * nz;
     const int sy = nx + 2, sz = (nx + 2) * (ny + 2);
-    double xr[NPT], rr_[NPT], qv[NPT];
+    double xr[NPT], rv[NPT], pv[NPT], sv[NPT];
     int pc_[NPT], dg[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -731,51 +770,66 @@ __device__ int cg_one_wave(GetB get_b, PutX put_x, double* pl, int nx, int ny, i
         const bool v = c < n;
         const int i = v ? c % nx : 0, j = v ? (c / nx) % ny : 0, kk = v ? c / (nx * ny) : 0;
         dg[k] = v ? cell_diag(i, j, kk, nx, ny, nz, sh) : 0;
-        pc_[k] = padded(i, j, kk, nx, ny);
+        // lanes without a cell point at the corner ghost (index 0): they read
+        // zeros and only ever store their residual, which stays 0
+        pc_[k] = v ? padded(i, j, kk, nx, ny) : 0;
         xr[k] = 0.0;
-        rr_[k] = v ? (double)get_b(c) : 0.0;
-        if (v) pl[pc_[k]] = rr_[k];
+        pv[k] = 0.0;
+        sv[k] = 0.0;
+        rv[k] = v ? (double)get_b(c) : 0.0;
+        if (v) rl[pc_[k]] = rv[k];
     }
-    double loc = 0.0;
+    double gamma = 0.0, dummy = 0.0;
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) loc += rr_[k] * rr_[k];
-    double rr = wave_sum_dpp(loc);
-    const double bnorm = sqrt(rr);
+    for (int k = 0; k < NPT; ++k) gamma += rv[k] * rv[k];
+    wave_sum2_dpp(gamma, dummy);
+    const double bound = rtol * rtol * gamma;     // ||r||^2 <= rtol^2 ||b||^2
+    double gamma_old = 1.0, alpha_old = 1.0;
     int it = 0;
-    if (bnorm > 0.0) {
+    if (gamma > 0.0) {
         while (it < maxit) {
-            double pv[NPT];
-            double pq = 0.0;
+            // w = S r, delta = (w, r); gamma = (r, r) is already known
+            double wv[NPT], nbs[NPT][6];
+            double delta = 0.0;
+            // all neighbour loads first (unconditional), then the arithmetic
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
-                const int c = pc_[k];
-                pv[k] = pl[c];
-                const double s = ((((pl[c - 1] + pl[c + 1]) + pl[c - sy]) + pl[c + sy]) + pl[c - sz]) + pl[c + sz];
-                qv[k] = dg[k] ? (double)dg[k] * pv[k] - s : 0.0;
-                pq += dg[k] ? pv[k] * qv[k] : 0.0;
+                const int c = dg[k] ? pc_[k] : sz + sy + 1;   // a ghost-surrounded safe index
+                nbs[k][0] = rl[c - 1];
+                nbs[k][1] = rl[c + 1];
+                nbs[k][2] = rl[c - sy];
+                nbs[k][3] = rl[c + sy];
+                nbs[k][4] = rl[c - sz];
+                nbs[k][5] = rl[c + sz];
             }
-            pq = wave_sum_dpp(pq);
-            const double alpha = rr / pq;
-            double loc2 = 0.0;
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
-                if (dg[k]) {
-                    xr[k] += alpha * pv[k];
-                    rr_[k] -= alpha * qv[k];
-                }
-                loc2 += rr_[k] * rr_[k];
+                const double sum = ((((nbs[k][0] + nbs[k][1]) + nbs[k][2]) + nbs[k][3]) + nbs[k][4]) + nbs[k][5];
+                const double mask = dg[k] ? 1.0 : 0.0;
+                wv[k] = mask * ((double)dg[k] * rv[k] - sum);
+                delta += rv[k] * wv[k];
             }
-            const double rr_new = wave_sum_dpp(loc2);
+            wave_sum2_dpp(delta, dummy);
+            const double beta = it == 0 ? 0.0 : gamma * fast_rcp(gamma_old);
+            const double alpha = gamma * fast_rcp(delta - beta * gamma * fast_rcp(alpha_old));
+            double g2 = 0.0, d2 = 0.0;
+            __builtin_amdgcn_wave_barrier();   // all lanes' reads of r precede its update below
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                pv[k] = rv[k] + beta * pv[k];
+                sv[k] = wv[k] + beta * sv[k];
+                xr[k] += alpha * pv[k];
+                rv[k] -= alpha * sv[k];
+                g2 += rv[k] * rv[k];
+                rl[pc_[k]] = rv[k];
+            }
+            __builtin_amdgcn_wave_barrier();
+            wave_sum2_dpp(g2, d2);
             ++it;
-            if (sqrt(rr_new) <= rtol * bnorm) break;
-            const double beta = rr_new / rr;
-            rr = rr_new;
-            // every lane has read p (its values are in pv); the wave's stores follow its loads
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int k = 0; k < NPT; ++k)
-                if (dg[k]) pl[pc_[k]] = rr_[k] + beta * pv[k];
-            __builtin_amdgcn_wave_barrier();
+            gamma_old = gamma;
+            alpha_old = alpha;
+            gamma = g2;
+            if (gamma <= bound) break;
         }
     }
 #pragma unroll
@@ -865,21 +919,30 @@ __device__ void bottom_smooth(T* ph, const T* bt, int nx, int ny, int nz, const 
             const int m = threadIdx.x + u * kBottomThreads;
             const bool v = m < half;
             const int ip = v ? m % hx : 0, j = v ? (m / hx) % ny : 0, k = v ? m / (hx * ny) : 0;
-            const int i = 2 * ip + ((j + k + colour) & 1);
+            const int i = 2 * ip + ((j + k + colour) & 1);   // entries without a cell only load (cell 0 or 1)
             pidx[colour][u] = padded(i, j, k, nx, ny);
             bidx[colour][u] = (k * ny + j) * nx + i;
             dg[colour][u] = v ? cell_diag(i, j, k, nx, ny, nz, sh) : 0;
         }
+    T inv[2][kBottomCpt];
+#pragma unroll
+    for (int colour = 0; colour < 2; ++colour)
+#pragma unroll
+        for (int u = 0; u < kBottomCpt; ++u) inv[colour][u] = dg[colour][u] ? T(1) / T(dg[colour][u]) : T(0);
     for (int sw = 0; sw < sweeps; ++sw) {
 #pragma unroll
         for (int colour = 0; colour < 2; ++colour) {
+            // loads of every owned cell first, then the updates (cells of one colour are independent)
+            T nv[kBottomCpt];
 #pragma unroll
             for (int u = 0; u < kBottomCpt; ++u) {
-                if (dg[colour][u] == 0) continue;
                 const int c = pidx[colour][u];
                 const T sum = ((((ph[c - 1] + ph[c + 1]) + ph[c - sy]) + ph[c + sy]) + ph[c - sz]) + ph[c + sz];
-                ph[c] = (bt[bidx[colour][u]] + sum) / T(dg[colour][u]);
+                nv[u] = (bt[bidx[colour][u]] + sum) * inv[colour][u];
             }
+#pragma unroll
+            for (int u = 0; u < kBottomCpt; ++u)
+                if (dg[colour][u]) ph[pidx[colour][u]] = nv[u];
             __syncthreads();
         }
     }
