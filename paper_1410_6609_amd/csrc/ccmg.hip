@@ -179,7 +179,7 @@ constexpr size_t kBottomMaxLds = 160 * 1024;
 template <typename T, int SPHI, int LOAD, int RES>
 bool launch_one(const PassParams<T>& P0, hipStream_t st)
 {
-    using Sh = PassShape<T, SPHI, RES, kM, kWY>;
+    using Sh = PassShape<T, SPHI, RES, kM, kWY, LOAD>;
     auto kern = k_pass<T, SPHI, LOAD, RES, kM, kWY>;
     static int per_cu = 0;
     if (per_cu == 0) {

@@ -182,23 +182,23 @@ __device__ void finish_norm(double s_r2, double s_b2, double* partials, Ctl* ctl
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double lane_prev(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double lane_next(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ float lane_prev(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float lane_next(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
 // an x-pair of cells as one vector access (x even, so 2*sizeof(T)-aligned)
@@ -248,7 +248,7 @@ constexpr int lcm_c(int a, int b) { return a / gcd_c(a, b) * b; }
 //   RES:  none | restriction of the residual to the next level's b-tilde |
 //         residual norm | residual norm + residual / sigma as FP32 | store r
 // ---------------------------------------------------------------------------
-template <typename T, int SPHI, int RES, int M, int WY>
+template <typename T, int SPHI, int RES, int M, int WY, int LOAD = LOAD_PHI>
 struct PassShape {
     static constexpr int S = SPHI + (RES != RES_NONE ? 1 : 0);   // stages after the load
     static constexpr int H = (S + 1) & ~1;                           // halo, even (restriction pairs)
@@ -261,9 +261,13 @@ struct PassShape {
     static constexpr int RB = S >= 4 ? RP : S + 1;                   // b ring planes
     // planes in flight: the five-stage passes have no registers to spare for a second one
     static constexpr int PD = CCMG_PREFETCH;
+    // The branch-free update (out-of-domain cells have 1/d = 0) issues fewer
+    // instructions, but in the five-stage passes that also load phi the
+    // compiler then runs out of registers; those keep the masked update.
     static constexpr int U = lcm_c(lcm_c(lcm_c(RP, RB), 2), PD);   // unrolled steps
     static constexpr int NT = 64 * WY;
     static constexpr int E1 = SPHI > 0 ? SPHI : 1;                   // single-value edge stages
+    static constexpr bool MASKED_UPDATE = sizeof(T) == 8 && S >= 5 && LOAD != LOAD_ZERO;
 };
 
 #ifndef CCMG_PASS_WAVES_PER_EU
@@ -273,7 +277,7 @@ struct PassShape {
 template <typename T, int SPHI, int LOAD, int RES, int M, int WY>
 __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassParams<T> P)
 {
-    using Sh = PassShape<T, SPHI, RES, M, WY>;
+    using Sh = PassShape<T, SPHI, RES, M, WY, LOAD>;
     constexpr int S = Sh::S, H = Sh::H, TX = Sh::TX, TY = Sh::TY, RP = Sh::RP, RB = Sh::RB, U = Sh::U;
     constexpr int NSTRIP = Sh::NSTRIP;
     static_assert(M % 2 == 0, "rows per thread must be even");
@@ -423,6 +427,23 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                         edge2[par][strip][1][xp][1] = ph[s0][M - 1][1];
                     }
                 }
+                // ---- all strip-edge inputs of this step were written before the last
+                // barrier (other parity buffer): read them at once, one LDS latency
+                T e_lo[Sh::E1], e_hi[Sh::E1];
+#pragma unroll
+                for (int s = 1; s <= SPHI; ++s) {
+                    const T* ein = &edge1[s - 1][par ^ 1][0][0][0];
+                    e_lo[s - 1] = strip > 0 ? ein[((strip - 1) * 2 + 1) * 32 + xp] : T(0);
+                    e_hi[s - 1] = strip < NSTRIP - 1 ? ein[((strip + 1) * 2 + 0) * 32 + xp] : T(0);
+                }
+                T e2lo[2], e2hi[2];
+                if constexpr (RES != RES_NONE) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        e2lo[c] = strip > 0 ? edge2[par ^ 1][strip - 1][1][xp][c] : T(0);
+                        e2hi[c] = strip < NSTRIP - 1 ? edge2[par ^ 1][strip + 1][0][xp][c] : T(0);
+                    }
+                }
                 // ---- stages 1..SPHI: colour half-sweeps, red ((x+y+z) even) first
 #pragma unroll
                 for (int s = 1; s <= SPHI; ++s) {
@@ -437,9 +458,8 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     int dz = 0;
                     if (p == 0) dz += P.sh[4];
                     if (p == nz - 1) dz += P.sh[5];
-                    const T* ein = &edge1[s - 1][par ^ 1][0][0][0];
-                    const T elo = strip > 0 ? ein[((strip - 1) * 2 + 1) * 32 + xp] : T(0);
-                    const T ehi = strip < NSTRIP - 1 ? ein[((strip + 1) * 2 + 0) * 32 + xp] : T(0);
+                    const T elo = e_lo[s - 1];
+                    const T ehi = e_hi[s - 1];
                     auto body = [&](auto zbt) {
                         constexpr bool ZB = decltype(zbt)::value;
 #pragma unroll
@@ -454,8 +474,10 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                             T inv;
                             if constexpr (ZB) inv = vrow[r] ? T(1) / T(dxy[r][o] + dz) : T(0);
                             else inv = inv0[r][o];
+                            // cells outside the domain have inv = 0, planes outside it stay zero
                             const T nv = (bb[sb][r][o] + sum) * inv;
-                            ph[sc][r][o] = (pin && vrow[r]) ? nv : ph[sc][r][o];
+                            if constexpr (Sh::MASKED_UPDATE) ph[sc][r][o] = (pin && vrow[r]) ? nv : ph[sc][r][o];
+                            else ph[sc][r][o] = pin ? nv : T(0);
                         }
                     };
                     if (dz != 0) body(std::true_type{});
@@ -496,12 +518,8 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     int dz = 0;
                     if (p == 0) dz += P.sh[4];
                     if (p == nz - 1) dz += P.sh[5];
-                    T elo[2], ehi[2];
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        elo[c] = strip > 0 ? edge2[par ^ 1][strip - 1][1][xp][c] : T(0);
-                        ehi[c] = strip < NSTRIP - 1 ? edge2[par ^ 1][strip + 1][0][xp][c] : T(0);
-                    }
+                    const T* elo = e2lo;
+                    const T* ehi = e2hi;
                     T res[M][2];
 #pragma unroll
                     for (int r = 0; r < M; ++r) {
