@@ -124,6 +124,7 @@ struct ccmg_solver {
     double prof_ms[8] = {0};
     int prof_n[8] = {0};
     // host mirrors
+    std::vector<char> ctl_host;
     std::vector<double> hist;
     int last_cycles = 0;
     std::string err;
@@ -207,27 +208,26 @@ bool launch_one(const PassParams<T>& P0, hipStream_t st)
 template <typename T, int SPHI>
 bool dispatch_sphi(int load, int res, const PassParams<T>& P, hipStream_t st)
 {
+    // the V-cycle uses: pre-smoothing from phi or zero (last pass restricts),
+    // post-smoothing from phi with or without the prolongation (the finest
+    // level's last pass reduces the norm; FP32 levels never do)
+    constexpr bool kNorm = sizeof(T) == 8;
     switch (load) {
     case LOAD_PHI:
-        switch (res) {
-        case RES_NONE: return launch_one<T, SPHI, LOAD_PHI, RES_NONE>(P, st);
-        case RES_RESTRICT: return launch_one<T, SPHI, LOAD_PHI, RES_RESTRICT>(P, st);
-        case RES_NORM: return launch_one<T, SPHI, LOAD_PHI, RES_NORM>(P, st);
-        default: return false;
-        }
+        if (res == RES_NONE) return launch_one<T, SPHI, LOAD_PHI, RES_NONE>(P, st);
+        if (res == RES_RESTRICT) return launch_one<T, SPHI, LOAD_PHI, RES_RESTRICT>(P, st);
+        if constexpr (kNorm)
+            if (res == RES_NORM) return launch_one<T, SPHI, LOAD_PHI, RES_NORM>(P, st);
+        return false;
     case LOAD_ZERO:
-        switch (res) {
-        case RES_NONE: return launch_one<T, SPHI, LOAD_ZERO, RES_NONE>(P, st);
-        case RES_RESTRICT: return launch_one<T, SPHI, LOAD_ZERO, RES_RESTRICT>(P, st);
-        default: return false;
-        }
+        if (res == RES_NONE) return launch_one<T, SPHI, LOAD_ZERO, RES_NONE>(P, st);
+        if (res == RES_RESTRICT) return launch_one<T, SPHI, LOAD_ZERO, RES_RESTRICT>(P, st);
+        return false;
     case LOAD_PROLONG:
-        switch (res) {
-        case RES_NONE: return launch_one<T, SPHI, LOAD_PROLONG, RES_NONE>(P, st);
-        case RES_RESTRICT: return launch_one<T, SPHI, LOAD_PROLONG, RES_RESTRICT>(P, st);
-        case RES_NORM: return launch_one<T, SPHI, LOAD_PROLONG, RES_NORM>(P, st);
-        default: return false;
-        }
+        if (res == RES_NONE) return launch_one<T, SPHI, LOAD_PROLONG, RES_NONE>(P, st);
+        if constexpr (kNorm)
+            if (res == RES_NORM) return launch_one<T, SPHI, LOAD_PROLONG, RES_NORM>(P, st);
+        return false;
     default: return false;
     }
 }
@@ -253,7 +253,6 @@ bool dispatch<double>(int sphi, int load, int res, const PassParams<double>& P, 
 template <>
 bool dispatch<float>(int sphi, int load, int res, const PassParams<float>& P, hipStream_t st)
 {
-    if (res == RES_NORM) return false;
     if (sphi == 2) return dispatch_sphi<float, 2>(load, res, P, st);
     if (sphi == 4) return dispatch_sphi<float, 4>(load, res, P, st);
     return false;
@@ -574,31 +573,44 @@ int read_ctl(ccmg_solver* s, CtlHead& h, int hist_upto)
     return CCMG_OK;
 }
 
+// Whole control block (header and history) to the host in one copy.
+int read_all(ccmg_solver* s, CtlHead& h)
+{
+    s->ctl_host.resize(sizeof(Ctl));
+    HIPCHK(s, hipMemcpyAsync(s->ctl_host.data(), s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    std::memcpy(&h, s->ctl_host.data(), sizeof h);
+    const Ctl* c = reinterpret_cast<const Ctl*>(s->ctl_host.data());
+    const int n = std::max(0, std::min(h.cycles + 1, kMaxHist));
+    s->hist.assign(c->hist, c->hist + n);
+    return CCMG_OK;
+}
+
 // Run the cycle loop after the initial residual pass.  `enqueue_step(k)`
-// enqueues cycle / refinement step k (k >= 1) ending with FIN_CYCLE(k).
+// enqueues cycle / refinement step k (k >= 1) ending with FIN_CYCLE(k).  The
+// first batch is enqueued right behind the initial pass without waiting (its
+// kernels return at once if the initial guess already satisfies the
+// tolerance); the host synchronises once per batch, and sizes the next batch
+// from the observed contraction.
 template <typename F>
 int run_loop(ccmg_solver* s, int max_cycles, F enqueue_step, CtlHead& h)
 {
     int k = 0;
-    int rc = read_ctl(s, h, -1);   // initial state (also catches a zero RHS)
-    if (rc) return rc;
-    if (h.done) return CCMG_OK;
     int batch = s->last_cycles > 0 ? s->last_cycles : 8;
-    while (k < max_cycles) {
-        batch = std::max(1, std::min(batch, max_cycles - k));
+    int rc;
+    for (;;) {
+        batch = std::max(0, std::min(batch, max_cycles - k));
         for (int i = 0; i < batch; ++i) {
             rc = enqueue_step(k + 1 + i);
             if (rc) return rc;
         }
         k += batch;
-        rc = read_ctl(s, h, -1);
+        rc = read_all(s, h);
         if (rc) return rc;
-        if (h.done) break;
-        // estimate the remaining cycles from the observed contraction
-        std::vector<double> hv(2);
+        if (h.done || k >= max_cycles) break;
+        // estimate the remaining cycles from the last contraction
         const int c = h.cycles;
-        HIPCHK(s, hipMemcpy(hv.data(), s->ctl->hist + (c - 1), 2 * sizeof(double), hipMemcpyDeviceToHost));
-        const double rate = (hv[0] > 0.0) ? hv[1] / hv[0] : 0.5;
+        const double rate = (c >= 1 && s->hist[c - 1] > 0.0) ? s->hist[c] / s->hist[c - 1] : 0.5;
         int need = 2;
         if (rate > 0.0 && rate < 1.0 && h.rel > 0.0)
             need = (int)std::ceil(std::log(h.rtol / h.rel) / std::log(rate));
@@ -610,8 +622,6 @@ int run_loop(ccmg_solver* s, int max_cycles, F enqueue_step, CtlHead& h)
 int finish_stats(ccmg_solver* s, const CtlHead& h, int inner_per_step, ccmg_stats* st,
                  std::chrono::steady_clock::time_point t0)
 {
-    int rc = read_ctl(s, const_cast<CtlHead&>(h), h.cycles);
-    if (rc) return rc;
     prof_collect(s, h.cycles);
     s->last_cycles = h.cycles > 0 ? h.cycles : s->last_cycles;
     if (st) {

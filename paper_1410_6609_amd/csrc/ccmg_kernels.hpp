@@ -458,6 +458,11 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     int dz = 0;
                     if (p == 0) dz += P.sh[4];
                     if (p == nz - 1) dz += P.sh[5];
+                    // Stage s is needed on planes [z0 - (S - s), z1 + (S - s)); outside, its
+                    // values are read only by later stages that are skipped as well
+                    // (the needed ranges nest), so the halo steps at the chunk ends run
+                    // only the stages that matter.
+                    if (p < z0 - (S - s) || p >= z1 + (S - s)) continue;
                     const T elo = e_lo[s - 1];
                     const T ehi = e_hi[s - 1];
                     auto body = [&](auto zbt) {
@@ -508,7 +513,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     }
                 }
                 // ---- residual stage at plane t - S (both cells of every pair)
-                if constexpr (RES != RES_NONE) {
+                if constexpr (RES != RES_NONE) if (t - S >= z0 && t - S < z1) {
                     const int p = t - S;
                     const int sc = (q - S + 2 * U) % RP;
                     const int sm = (q - S - 1 + 2 * U) % RP;
