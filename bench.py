@@ -14,6 +14,7 @@ oracle's rate on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +30,39 @@ import paper_1410_6609_amd as pkg  # noqa: E402
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+KERNEL_NAMES = {   # finest-level passes of a V(2,2) cycle, two sweeps fused per pass
+    "pre": "void k_pass<double, 4, 0, 1, 2, 8>",
+    "post": "void k_pass<double, 4, 2, 2, 2, 8>",
+}
+
+
+def kernel_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for f in ("paper_1410_6609_amd/csrc/ccmg_kernels.hpp", "paper_1410_6609_amd/csrc/ccmg.hip"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, which: str):
+    """HBM bytes per launch of the finest-level pass from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when the
+    summary is missing or was taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    data = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    if data.get("kernel_source_sha256") != kernel_sources_sha256():
+        return None
+    best = None
+    for key, v in data["kernels"].items():
+        name, grid = key.rsplit("|", 1)
+        if name.startswith(KERNEL_NAMES[which]) and (best is None or int(grid) > best[0]):
+            best = (int(grid), v["fetch_bytes"] + v["write_bytes"])
+    return None if best is None else best[1]
 
 
 def log(*a):
@@ -136,22 +170,25 @@ def main():
     # roofline of the dominant kernel: the finest-level fused pass with the larger total time
     cells = w.cells
     passes = [
-        ("pre-smoothing pass (2 RB-GS sweeps + residual + restriction), finest level", ms0, n0,
+        ("pre", "pre-smoothing pass (2 RB-GS sweeps + residual + restriction), finest level", ms0, n0,
          8 + 8 + 8 + 1),
-        ("post-smoothing pass (prolongation + 2 RB-GS sweeps + residual norm), finest level", ms1, n1,
+        ("post", "post-smoothing pass (prolongation + 2 RB-GS sweeps + residual norm), finest level", ms1, n1,
          8 + 1 + 8 + 8),
     ]
-    name, ms_k, n_k, bpc = max(passes, key=lambda p: p[1])
+    which, name, ms_k, n_k, bpc = max(passes, key=lambda p: p[2])
     avg_s = ms_k / max(n_k, 1) / 1e3
     bytes_per_launch = bpc * cells
     achieved = bytes_per_launch / avg_s / 1e9
+    hbm = measured_traffic(w.name, which)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if hbm is None else round(hbm / avg_s / 1e9, 1),
                 "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_k,
-                "algorithmic_bytes_per_cell": bpc}
-    other = [p for p in passes if p[0] != name][0]
-    roofline["other_pass"] = {"kernel": other[0], "avg_launch_us": round(other[1] / max(other[2], 1) * 1e3, 2),
-                              "achieved_GBs": round(other[3] * cells / (other[1] / max(other[2], 1) / 1e3) / 1e9, 1)}
+                "algorithmic_bytes_per_cell": bpc, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "hbm_bytes_per_launch": hbm}
+    other = [p for p in passes if p[0] != which][0]
+    roofline["other_pass"] = {"kernel": other[1], "avg_launch_us": round(other[2] / max(other[3], 1) * 1e3, 2),
+                              "achieved_GBs": round(other[4] * cells / (other[2] / max(other[3], 1) / 1e3) / 1e9, 1)}
 
     out = {
         "metric": "fine-grid unknowns solved/s to 1e-10 rel. residual",
