@@ -62,6 +62,8 @@ def lib() -> ctypes.CDLL:
             "or_fold": ([I, I, I, D, ip, dp, dp, dp], None),
             "or_deposit": ([I, I, I, D, I, dp, dp, dp, D, dp, lp], None),
             "or_dq": ([I, I, I, D, I, dp, dp, D, dp, dp], None),
+            "or_deposit_sub": ([I, I, I, D, I, dp, dp, dp, D, I, I, dp, dp], None),
+            "or_dq_sub": ([I, I, I, D, I, dp, dp, D, I, I, dp, dp], None),
             "or_solve": ([I, I, I, D, ip, I, I, I, D, D, I, dp, dp, D, I, dp, ip], I),
             "or_solve_ir": ([I, I, I, D, ip, I, I, I, D, D, I, I, dp, dp, D, I, dp, ip], I),
         }
@@ -188,6 +190,28 @@ def dq(lam, h, centers, radii, eps: float = 1.0) -> np.ndarray:
     centers, radii = _f64(centers).reshape(-1, 3), _f64(radii)
     out = np.zeros(radii.shape[0])
     lib().or_dq(nx, ny, nz, h, radii.shape[0], _dp(centers), _dp(radii), eps, _dp(lam), _dp(out))
+    return out
+
+
+def deposit_sub(shape, h, centers, radii, q, eps: float = 1.0, subsample: int = 2, mode: int = 0):
+    """Sub-sampled deposition; returns (f = rho/eps, W_s = summed overlap ratios)."""
+    nx, ny, nz = shape
+    centers, radii, q = _f64(centers).reshape(-1, 3), _f64(radii), _f64(q)
+    n = radii.shape[0]
+    f = np.empty((nz, ny, nx))
+    wsum = np.zeros(n)
+    lib().or_deposit_sub(nx, ny, nz, h, n, _dp(centers), _dp(radii), _dp(q), eps, subsample, mode, _dp(f),
+                         _dp(wsum))
+    return f, wsum
+
+
+def dq_sub(lam, h, centers, radii, eps: float = 1.0, subsample: int = 2, mode: int = 0) -> np.ndarray:
+    lam = _f64(lam)
+    nx, ny, nz = _shape(lam)
+    centers, radii = _f64(centers).reshape(-1, 3), _f64(radii)
+    out = np.zeros(radii.shape[0])
+    lib().or_dq_sub(nx, ny, nz, h, radii.shape[0], _dp(centers), _dp(radii), eps, subsample, mode, _dp(lam),
+                    _dp(out))
     return out
 
 

@@ -39,12 +39,17 @@
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no contraction, so
  * every operation rounds exactly as written).
  */
+#define _USE_MATH_DEFINES
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
 #endif
 
 #define OR_DIRICHLET 0
@@ -440,6 +445,105 @@ void or_dq(int nx, int ny, int nz, double h, int n, const double* centers, const
                 for (int i = ilo; i <= ihi; ++i)
                     if (inside_ball(i, j, k, h, c, R)) acc += lambda[IDX(&L, i, j, k)];
         dq[s] = acc / (eps * (double)ns * h * h * h);
+    }
+}
+
+/* Sub-sampled deposition (Sec. 2.4, "Subsampling"): each cell is divided
+ * equidistantly into sf^3 sub-cells, and its overlap ratio w_{s,c} with
+ * sphere s is the fraction of sub-cell centres inside the closed ball
+ * (sub-cell centre ((i + (a + 1/2)/sf) h, ...), a = 0..sf-1; same
+ * left-to-right, uncontracted distance test as above).
+ *   mode 0 (spread):  f_c += q_s w_{s,c} / (eps W_s h^3), W_s = sum_c w_{s,c}
+ *                     (the charge is conserved exactly);
+ *   mode 1 (volume):  f_c += q_s w_{s,c} / (eps V_s), V_s = 4/3 pi R_s^3
+ *                     (the paper's density charge/volume times the ratio).
+ * weight_sum[s] receives W_s (may be NULL).  Spheres are added in index
+ * order; a sphere with W_s = 0 deposits nothing in mode 0. */
+static int sub_inside(int i, int j, int k, int a, int b, int c, int sf, double h, const double* ctr, double R)
+{
+    const double dx = ((double)i + ((double)a + 0.5) / (double)sf) * h - ctr[0];
+    const double dy = ((double)j + ((double)b + 0.5) / (double)sf) * h - ctr[1];
+    const double dz = ((double)k + ((double)c + 0.5) / (double)sf) * h - ctr[2];
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    return d2 <= R * R;
+}
+
+static double cell_ratio(int i, int j, int k, int sf, double h, const double* ctr, double R)
+{
+    int cnt = 0;
+    for (int c = 0; c < sf; ++c)
+        for (int b = 0; b < sf; ++b)
+            for (int a = 0; a < sf; ++a) cnt += sub_inside(i, j, k, a, b, c, sf, h, ctr, R);
+    return (double)cnt / (double)(sf * sf * sf);
+}
+
+static double sphere_weight(int nx, int ny, int nz, double h, const double* ctr, double R, int sf)
+{
+    int ilo, ihi, jlo, jhi, klo, khi;
+    axis_range(ctr[0], R, h, nx, &ilo, &ihi);
+    axis_range(ctr[1], R, h, ny, &jlo, &jhi);
+    axis_range(ctr[2], R, h, nz, &klo, &khi);
+    double W = 0.0;
+    for (int k = klo; k <= khi; ++k)
+        for (int j = jlo; j <= jhi; ++j)
+            for (int i = ilo; i <= ihi; ++i) W += cell_ratio(i, j, k, sf, h, ctr, R);
+    return W;
+}
+
+static double sphere_norm(int mode, double eps, double W, double R, double h)
+{
+    if (mode == 0) return eps * W * h * h * h;
+    return eps * ((4.0 / 3.0) * M_PI * R * R * R);
+}
+
+void or_deposit_sub(int nx, int ny, int nz, double h, int n, const double* centers, const double* radii,
+                    const double* q, double eps, int sf, int mode, double* f, double* weight_sum)
+{
+    const or_level L = make_level(nx, ny, nz, h, 0, (const int[6]){0, 0, 0, 0, 0, 0});
+    memset(f, 0, or_cells(&L) * sizeof(double));
+    for (int s = 0; s < n; ++s) {
+        const double* c = centers + 3 * (size_t)s;
+        const double R = radii[s];
+        const double W = sphere_weight(nx, ny, nz, h, c, R, sf);
+        if (weight_sum) weight_sum[s] = W;
+        if (W == 0.0) continue;
+        const double norm = sphere_norm(mode, eps, W, R, h);
+        int ilo, ihi, jlo, jhi, klo, khi;
+        axis_range(c[0], R, h, nx, &ilo, &ihi);
+        axis_range(c[1], R, h, ny, &jlo, &jhi);
+        axis_range(c[2], R, h, nz, &klo, &khi);
+        for (int k = klo; k <= khi; ++k)
+            for (int j = jlo; j <= jhi; ++j)
+                for (int i = ilo; i <= ihi; ++i) {
+                    const double w = cell_ratio(i, j, k, sf, h, c, R);
+                    if (w > 0.0) f[IDX(&L, i, j, k)] += q[s] * w / norm;
+                }
+    }
+}
+
+/* Gradient of a loss with respect to the charges for the sub-sampled
+ * deposition: dL/dq_s = sum_c lambda_c w_{s,c} / norm_s. */
+void or_dq_sub(int nx, int ny, int nz, double h, int n, const double* centers, const double* radii, double eps,
+               int sf, int mode, const double* lambda, double* dq)
+{
+    const or_level L = make_level(nx, ny, nz, h, 0, (const int[6]){0, 0, 0, 0, 0, 0});
+    for (int s = 0; s < n; ++s) {
+        const double* c = centers + 3 * (size_t)s;
+        const double R = radii[s];
+        const double W = sphere_weight(nx, ny, nz, h, c, R, sf);
+        if (W == 0.0 && mode == 0) { dq[s] = 0.0; continue; }
+        int ilo, ihi, jlo, jhi, klo, khi;
+        axis_range(c[0], R, h, nx, &ilo, &ihi);
+        axis_range(c[1], R, h, ny, &jlo, &jhi);
+        axis_range(c[2], R, h, nz, &klo, &khi);
+        double acc = 0.0;
+        for (int k = klo; k <= khi; ++k)
+            for (int j = jlo; j <= jhi; ++j)
+                for (int i = ilo; i <= ihi; ++i) {
+                    const double w = cell_ratio(i, j, k, sf, h, c, R);
+                    if (w > 0.0) acc += lambda[IDX(&L, i, j, k)] * w;
+                }
+        dq[s] = acc / sphere_norm(mode, eps, W, R, h);
     }
 }
 
