@@ -130,6 +130,50 @@ int ccmg_level_dims(const ccmg_solver* s, int l, int dims_out[3]);
 int ccmg_deposit_charges(ccmg_solver* s, int n, const double* d_centers, const double* d_radii,
                          const double* d_q, double eps, double* d_f, int* d_counts);
 
+/* Normalisations of the sub-sampled deposition */
+enum {
+    CCMG_CHARGE_SPREAD = 0, /* rho = q w / (W h^3): the sphere's charge is conserved exactly */
+    CCMG_CHARGE_VOLUME = 1  /* rho = q w / (4/3 pi R^3): the paper's charge density q / V per
+                               overlapped volume fraction (total charge q W h^3 / V) */
+};
+#define CCMG_MAX_SUBSAMPLE 8
+
+/* Sub-sampled charge deposition (Sec. 2.4, "Subsampling"; accuracy of the
+ * factors in Sec. 6.3): every cell is split equidistantly into subsample^3
+ * sub-cells, and its overlap ratio w with sphere s is the fraction of the
+ * sub-cell centres ((i + (a + 1/2)/subsample) h, ...), a = 0..subsample-1,
+ * that lie in the closed ball (distance test (dx*dx + dy*dy) + dz*dz <= R*R
+ * without contraction).  W_s = sum over cells of w.  Each overlapped cell
+ * receives q_s w / (eps norm_s) in d_f (overwritten; overlapping spheres add
+ * in unspecified order), with norm_s = W_s h^3 (CCMG_CHARGE_SPREAD) or
+ * 4/3 pi R_s^3 (CCMG_CHARGE_VOLUME).  A sphere with W_s = 0 deposits nothing.
+ * subsample = 1 with CCMG_CHARGE_SPREAD equals ccmg_deposit_charges, with
+ * CCMG_CHARGE_VOLUME the paper's naive q / V density.  d_weights (nullable,
+ * double[n]) receives W_s.  subsample in 1..CCMG_MAX_SUBSAMPLE, else E_ARG. */
+int ccmg_deposit_charges_sub(ccmg_solver* s, int n, const double* d_centers, const double* d_radii,
+                             const double* d_q, double eps, int subsample, int mode, double* d_f,
+                             double* d_weights);
+
+/* Charge gradient of a loss for the sub-sampled deposition: given the adjoint
+ * field d_lambda = dL/df (from ccmg_adjoint_solve), d_dq[s] = dL/dq_s =
+ * sum over cells of lambda_c w_{s,c} / (eps norm_s), with w, norm_s and the
+ * arguments as in ccmg_deposit_charges_sub (0 for a sphere with W_s = 0 in
+ * CCMG_CHARGE_SPREAD mode).  Enqueued without waiting. */
+int ccmg_charge_gradient(ccmg_solver* s, int n, const double* d_centers, const double* d_radii, double eps,
+                         int subsample, int mode, const double* d_lambda, double* d_dq);
+
+/* Per-cell boundary values on one face (Sec. 2.4, "Boundary conditions"; the
+ * validation of Sec. 6.3 sets them to the analytic potential): d_values holds
+ * one value per boundary cell of the face, x faces [nz][ny], y faces [nz][nx],
+ * z faces [ny][nx] (first index slowest); each is the Dirichlet value at the
+ * face centre or the outward normal derivative there, by the face's kind.
+ * The values are copied (stream-ordered) into the workspace, so d_values may
+ * be freed once the copy has run; they replace the face's constant value in
+ * every later forward fold (the adjoint solve keeps homogeneous values).
+ * d_values = NULL restores the constant value.  Needs the workspace
+ * (E_STATE otherwise). */
+int ccmg_set_face_values(ccmg_solver* s, int face, const double* d_values);
+
 /* One V(nu1,nu2)-cycle on d_phi (in/out) for the right-hand side d_f (= rho/eps,
  * boundary values taken from the faces).  rel_res_out (nullable): the relative
  * residual ||b - A phi|| / ||b|| after the cycle (synchronises). */

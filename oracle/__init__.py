@@ -62,6 +62,8 @@ def lib() -> ctypes.CDLL:
             "or_fold": ([I, I, I, D, ip, dp, dp, dp], None),
             "or_deposit": ([I, I, I, D, I, dp, dp, dp, D, dp, lp], None),
             "or_dq": ([I, I, I, D, I, dp, dp, D, dp, dp], None),
+            "or_fold_field": ([I, I, I, D, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_void_p), dp, dp], None),
             "or_deposit_sub": ([I, I, I, D, I, dp, dp, dp, D, I, I, dp, dp], None),
             "or_dq_sub": ([I, I, I, D, I, dp, dp, D, I, I, dp, dp], None),
             "or_solve": ([I, I, I, D, ip, I, I, I, D, D, I, dp, dp, D, I, dp, ip], I),
@@ -169,6 +171,21 @@ def fold(f, h, kinds, values) -> np.ndarray:
     nx, ny, nz = _shape(f)
     vals = (ctypes.c_double * 6)(*[float(v) for v in values])
     lib().or_fold(nx, ny, nz, h, _kinds(kinds), vals, _dp(f), _dp(b))
+    return b
+
+
+def fold_field(f, h, kinds, values, faces) -> np.ndarray:
+    """Fold with per-cell boundary values; faces[fc] is None (constant
+    values[fc]) or an array of the face's shape: x faces (nz, ny), y faces
+    (nz, nx), z faces (ny, nx)."""
+    f = _f64(f)
+    b = np.empty_like(f)
+    nx, ny, nz = _shape(f)
+    shapes = [(nz, ny)] * 2 + [(nz, nx)] * 2 + [(ny, nx)] * 2
+    keep = [None if a is None else _f64(a).reshape(shapes[i]) for i, a in enumerate(faces)]
+    ptrs = (ctypes.c_void_p * 6)(*[None if a is None else a.ctypes.data for a in keep])
+    vals = (ctypes.c_double * 6)(*[float(v) for v in values])
+    lib().or_fold_field(nx, ny, nz, h, _kinds(kinds), vals, ptrs, _dp(f), _dp(b))
     return b
 
 

@@ -361,6 +361,35 @@ void or_fold(int nx, int ny, int nz, double h, const int* kinds, const double* v
             }
 }
 
+/* Boundary folding with per-cell boundary values (Sec. 2.4, "Boundary
+ * conditions"; Sec. 6.3 sets the Dirichlet values of the validation domain to
+ * the analytic potential at the boundary).  face[fc] == NULL uses the
+ * constant values[fc]; otherwise it holds one value per boundary face of the
+ * cells on that side: x faces [nz][ny], y faces [nz][nx], z faces [ny][nx]
+ * (the first index slowest).  The value is the boundary value g at the face
+ * centre (Dirichlet) or the outward normal derivative there (Neumann). */
+void or_fold_field(int nx, int ny, int nz, double h, const int* kinds, const double* values,
+                   const double* const* face, const double* f, double* b)
+{
+    or_level L = make_level(nx, ny, nz, h, 0, kinds);
+    for (size_t c = 0; c < or_cells(&L); ++c) b[c] = f[c];
+    for (int fc = 0; fc < 6; ++fc) {
+        const int ax = fc / 2, hi = fc % 2;
+        const int n0 = ax == 0 ? ny : nx;          /* fastest index on the face */
+        const int n1 = ax == 2 ? ny : nz;
+        for (int v = 0; v < n1; ++v)
+            for (int u = 0; u < n0; ++u) {
+                const double g = face[fc] ? face[fc][(size_t)v * n0 + u] : values[fc];
+                const double t = kinds[fc] == OR_DIRICHLET ? 2.0 * g / (h * h) : g / h;
+                int i, j, k;
+                if (ax == 0)      { i = hi ? nx - 1 : 0; j = u; k = v; }
+                else if (ax == 1) { j = hi ? ny - 1 : 0; i = u; k = v; }
+                else              { k = hi ? nz - 1 : 0; i = u; j = v; }
+                b[IDX(&L, i, j, k)] += t;
+            }
+    }
+}
+
 /* Is the centre of cell (i,j,k) inside the closed ball (c, R)?  Evaluated as
  * dx*dx + dy*dy + dz*dz <= R*R, left to right, no contraction. */
 static int inside_ball(int i, int j, int k, double h, const double* c, double R)
@@ -468,26 +497,33 @@ static int sub_inside(int i, int j, int k, int a, int b, int c, int sf, double h
     return d2 <= R * R;
 }
 
-static double cell_ratio(int i, int j, int k, int sf, double h, const double* ctr, double R)
+static int sub_count(int i, int j, int k, int sf, double h, const double* ctr, double R)
 {
     int cnt = 0;
     for (int c = 0; c < sf; ++c)
         for (int b = 0; b < sf; ++b)
             for (int a = 0; a < sf; ++a) cnt += sub_inside(i, j, k, a, b, c, sf, h, ctr, R);
-    return (double)cnt / (double)(sf * sf * sf);
+    return cnt;
 }
 
+static double cell_ratio(int i, int j, int k, int sf, double h, const double* ctr, double R)
+{
+    return (double)sub_count(i, j, k, sf, h, ctr, R) / (double)(sf * sf * sf);
+}
+
+/* W_s = sum_c w_{s,c}, formed as (total sub-cell count) / sf^3: the same sum
+ * with a single rounding, independent of the summation order. */
 static double sphere_weight(int nx, int ny, int nz, double h, const double* ctr, double R, int sf)
 {
     int ilo, ihi, jlo, jhi, klo, khi;
     axis_range(ctr[0], R, h, nx, &ilo, &ihi);
     axis_range(ctr[1], R, h, ny, &jlo, &jhi);
     axis_range(ctr[2], R, h, nz, &klo, &khi);
-    double W = 0.0;
+    long long total = 0;
     for (int k = klo; k <= khi; ++k)
         for (int j = jlo; j <= jhi; ++j)
-            for (int i = ilo; i <= ihi; ++i) W += cell_ratio(i, j, k, sf, h, ctr, R);
-    return W;
+            for (int i = ilo; i <= ihi; ++i) total += sub_count(i, j, k, sf, h, ctr, R);
+    return (double)total / (double)(sf * sf * sf);
 }
 
 static double sphere_norm(int mode, double eps, double W, double R, double h)

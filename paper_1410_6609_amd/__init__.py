@@ -20,12 +20,14 @@ from typing import Optional, Sequence, Tuple
 import torch
 
 __all__ = [
-    "DIRICHLET", "NEUMANN", "FP64", "FP32_IR", "CcmgError", "Options", "Stats", "Solver",
+    "DIRICHLET", "NEUMANN", "FP64", "FP32_IR", "SPREAD", "VOLUME", "CcmgError", "Options", "Stats", "Solver",
     "PoissonFn", "RhsSolveFn", "lib", "LIB_PATH", "exported_symbols",
 ]
 
 DIRICHLET, NEUMANN = 0, 1
 FP64, FP32_IR = 0, 1
+SPREAD, VOLUME = 0, 1   # normalisations of the sub-sampled deposition
+MAX_SUBSAMPLE = 8
 OK, E_ARG, E_DIMS, E_SINGULAR, E_HIP, E_NONFINITE, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 _ERR_NAMES = {E_ARG: "E_ARG", E_DIMS: "E_DIMS", E_SINGULAR: "E_SINGULAR", E_HIP: "E_HIP",
               E_NONFINITE: "E_NONFINITE", E_NOCONV: "E_NOCONV", E_STATE: "E_STATE"}
@@ -99,6 +101,11 @@ _SIGS = {
     "ccmg_num_levels": ([_VP], ctypes.c_int),
     "ccmg_level_dims": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "ccmg_deposit_charges": ([_VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_double, _VP, _VP], ctypes.c_int),
+    "ccmg_deposit_charges_sub": ([_VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                  _VP, _VP], ctypes.c_int),
+    "ccmg_charge_gradient": ([_VP, ctypes.c_int, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.c_int, _VP, _VP],
+                             ctypes.c_int),
+    "ccmg_set_face_values": ([_VP, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_vcycle": ([_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ccmg_solve": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
     "ccmg_adjoint_solve": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_double, _VP, _VP,
@@ -223,17 +230,50 @@ class Solver:
 
     # -- the method -----------------------------------------------------------
     def deposit(self, centers, radii, q, eps: float = 1.0, out: Optional[torch.Tensor] = None,
-                counts: bool = False):
-        """f = rho / eps from charged spheres (naive volume mapping)."""
+                counts: bool = False, subsample: int = 1, mode: int = SPREAD):
+        """f = rho / eps from charged spheres.  subsample = 1 and mode SPREAD is
+        the naive volume mapping (counts: n_s per sphere, int32); otherwise the
+        sub-sampled deposition (counts: the summed overlap ratios W_s, float64)."""
         centers, radii = self._spheres(centers, radii)
         q = q.to(self.device, torch.float64).contiguous().reshape(-1)
         n = radii.shape[0]
         f = self.zeros() if out is None else self._field(out, "out")
-        cnt = torch.zeros(n, dtype=torch.int32, device=self.device) if counts else None
         self._bind_stream()
-        self._check(lib().ccmg_deposit_charges(self._h, n, _ptr(centers), _ptr(radii), _ptr(q), float(eps),
-                                               _ptr(f), _ptr(cnt)))
+        if subsample == 1 and mode == SPREAD:
+            cnt = torch.zeros(n, dtype=torch.int32, device=self.device) if counts else None
+            self._check(lib().ccmg_deposit_charges(self._h, n, _ptr(centers), _ptr(radii), _ptr(q), float(eps),
+                                                   _ptr(f), _ptr(cnt)))
+        else:
+            cnt = torch.zeros(n, dtype=torch.float64, device=self.device) if counts else None
+            self._check(lib().ccmg_deposit_charges_sub(self._h, n, _ptr(centers), _ptr(radii), _ptr(q), float(eps),
+                                                       int(subsample), int(mode), _ptr(f), _ptr(cnt)))
         return (f, cnt) if counts else f
+
+    def charge_gradient(self, lam: torch.Tensor, centers, radii, eps: float = 1.0, subsample: int = 1,
+                        mode: int = SPREAD) -> torch.Tensor:
+        """dL/dq per sphere from the adjoint field lam = dL/df."""
+        lam = self._field(lam, "lam")
+        c, r = self._spheres(centers, radii)
+        dq = torch.zeros(r.shape[0], dtype=torch.float64, device=self.device)
+        self._bind_stream()
+        self._check(lib().ccmg_charge_gradient(self._h, r.shape[0], _ptr(c), _ptr(r), float(eps), int(subsample),
+                                               int(mode), _ptr(lam), _ptr(dq)))
+        return dq
+
+    def set_face_values(self, face: int, values: Optional[torch.Tensor]) -> None:
+        """Per-cell boundary values of one face (None: back to the constant):
+        x faces (nz, ny), y faces (nz, nx), z faces (ny, nx)."""
+        nx, ny, nz = self.shape
+        shape = [(nz, ny)] * 2 + [(nz, nx)] * 2 + [(ny, nx)] * 2
+        v = None
+        if values is not None:
+            v = values.to(self.device, torch.float64).contiguous()
+            if tuple(v.shape) != shape[face]:
+                raise ValueError(f"face {face} values must have shape {shape[face]}")
+        self._bind_stream()
+        self._check(lib().ccmg_set_face_values(self._h, int(face), _ptr(v)))
+        self._face_keep = getattr(self, "_face_keep", {})
+        self._face_keep[face] = v   # the copy is stream-ordered: keep the source until it ran
 
     def solve(self, f: torch.Tensor, phi: Optional[torch.Tensor] = None, rtol: float = 1e-10,
               max_cycles: int = 100, check: bool = True):
@@ -258,10 +298,12 @@ class Solver:
 
     def adjoint(self, g: torch.Tensor, centers=None, radii=None, eps: float = 1.0, rtol: float = 1e-10,
                 max_cycles: int = 100, want_drho: bool = False, lam: Optional[torch.Tensor] = None,
-                check: bool = True):
-        """lambda = A^{-1} g; optional dL/dq per sphere and dL/drho.  Returns (lam, dq, drho, Stats)."""
+                check: bool = True, subsample: int = 1, mode: int = SPREAD):
+        """lambda = A^{-1} g; optional dL/dq per sphere (for the deposition with
+        the same subsample and mode) and dL/drho.  Returns (lam, dq, drho, Stats)."""
         g = self._field(g, "g")
         lam = self.zeros() if lam is None else self._field(lam, "lam")
+        naive = subsample == 1 and mode == SPREAD
         n = 0
         dq = None
         c = r = None
@@ -272,10 +314,15 @@ class Solver:
         drho = self.zeros() if want_drho else None
         st = _Stats()
         self._bind_stream()
-        rc = lib().ccmg_adjoint_solve(self._h, _ptr(g), _ptr(lam), n, _ptr(c), _ptr(r), float(eps), _ptr(dq),
-                                      _ptr(drho), float(rtol), int(max_cycles), ctypes.byref(st))
+        nn = n if naive else 0
+        rc = lib().ccmg_adjoint_solve(self._h, _ptr(g), _ptr(lam), nn, _ptr(c), _ptr(r), float(eps),
+                                      _ptr(dq) if naive else None, _ptr(drho), float(rtol), int(max_cycles),
+                                      ctypes.byref(st))
         if check:
             self._check(rc)
+        if n > 0 and not naive and rc in (OK, E_NOCONV):
+            self._check(lib().ccmg_charge_gradient(self._h, n, _ptr(c), _ptr(r), float(eps), int(subsample),
+                                                   int(mode), _ptr(lam), _ptr(dq)))
         return lam, dq, drho, Stats(st.cycles, st.inner_cycles, st.rel_res0, st.rel_res, st.seconds, rc)
 
     def residual(self, phi: torch.Tensor, f: torch.Tensor, want_field: bool = True):
@@ -315,10 +362,11 @@ class PoissonFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, q, centers, radii, solver: Solver, eps: float = 1.0, rtol: float = 1e-10,
-                max_cycles: int = 100):
-        f = solver.deposit(centers, radii, q, eps)
+                max_cycles: int = 100, subsample: int = 1, mode: int = SPREAD):
+        f = solver.deposit(centers, radii, q, eps, subsample=subsample, mode=mode)
         phi, st = solver.solve(f, rtol=rtol, max_cycles=max_cycles)
         ctx.solver, ctx.eps, ctx.rtol, ctx.max_cycles = solver, eps, rtol, max_cycles
+        ctx.subsample, ctx.mode = subsample, mode
         ctx.save_for_backward(centers, radii)
         ctx.stats = st
         return phi
@@ -327,8 +375,9 @@ class PoissonFn(torch.autograd.Function):
     def backward(ctx, grad_phi):
         centers, radii = ctx.saved_tensors
         g = grad_phi.contiguous().to(torch.float64)
-        _, dq, _, _ = ctx.solver.adjoint(g, centers, radii, ctx.eps, ctx.rtol, ctx.max_cycles)
-        return dq, None, None, None, None, None, None
+        _, dq, _, _ = ctx.solver.adjoint(g, centers, radii, ctx.eps, ctx.rtol, ctx.max_cycles,
+                                         subsample=ctx.subsample, mode=ctx.mode)
+        return dq, None, None, None, None, None, None, None, None
 
 
 class RhsSolveFn(torch.autograd.Function):

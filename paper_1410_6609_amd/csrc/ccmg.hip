@@ -116,6 +116,8 @@ struct ccmg_solver {
     Ctl* ctl = nullptr;
     double* partials = nullptr;
     int max_partials = 0;
+    double* face_vals[6] = {};   // per-cell boundary values (workspace)
+    bool face_on[6] = {};        // face uses face_vals instead of bc[].value
     // kernel timing (ccmg_profile_*)
     bool prof = false;
     struct ProfRec { int cycle, which; hipEvent_t a, b; };
@@ -526,13 +528,21 @@ int enqueue_ctl_init(ccmg_solver* s, double rtol)
 int enqueue_fold(ccmg_solver* s, const double* f, bool homogeneous)
 {
     const LevelBuf& B = s->lv[0];
-    double t[6];
+    FoldParams P{};
+    P.f = f;
+    P.bt = B.b;
+    P.nx = B.nx;
+    P.ny = B.ny;
+    P.nz = B.nz;
+    P.h = s->h;
+    P.h2 = s->h * s->h;
     for (int fc = 0; fc < 6; ++fc) {
         const double g = homogeneous ? 0.0 : s->bc[fc].value;
-        t[fc] = s->bc[fc].kind == CCMG_DIRICHLET ? 2.0 * g / (s->h * s->h) : g / s->h;
+        P.t[fc] = s->bc[fc].kind == CCMG_DIRICHLET ? 2.0 * g / (s->h * s->h) : g / s->h;
+        P.face[fc] = (!homogeneous && s->face_on[fc]) ? s->face_vals[fc] : nullptr;
+        P.dirichlet[fc] = s->bc[fc].kind == CCMG_DIRICHLET;
     }
-    hipLaunchKernelGGL(k_fold, dim3(grid1d(B.n)), dim3(256), 0, s->stream, f, B.b, B.nx, B.ny, B.nz, s->h * s->h,
-                       t[0], t[1], t[2], t[3], t[4], t[5], s->ctl);
+    hipLaunchKernelGGL(k_fold, dim3(grid1d(B.n)), dim3(256), 0, s->stream, P);
     LAUNCHCHK(s);
     return CCMG_OK;
 }
@@ -693,6 +703,13 @@ int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_
 // FP64 b-tilde / ping-pong / home buffers (finest level, and every level in
 // FP64 mode) and the FP32 hierarchy (FP32-IR mode).  With base == nullptr
 // only the size is computed.  Returns the bytes used.
+// boundary cells of face fc: x faces ny*nz, y faces nx*nz, z faces nx*ny
+size_t face_cells(const ccmg_solver* s, int fc)
+{
+    const size_t nx = s->nx, ny = s->ny, nz = s->nz;
+    return fc < 2 ? ny * nz : fc < 4 ? nx * nz : nx * ny;
+}
+
 size_t layout_workspace(ccmg_solver* s, char* base)
 {
     size_t off = 0;
@@ -700,6 +717,10 @@ size_t layout_workspace(ccmg_solver* s, char* base)
     Ctl* ctl = (Ctl*)take(sizeof(Ctl));
     double* part = (double*)take(2 * sizeof(double) * (size_t)s->max_partials);
     if (base) { s->ctl = ctl; s->partials = part; }
+    for (int fc = 0; fc < 6; ++fc) {
+        double* fv = (double*)take(sizeof(double) * face_cells(s, fc));
+        if (base) s->face_vals[fc] = fv;
+    }
     for (int l = 0; l < s->L; ++l) {
         LevelBuf& B = s->lv[l];
         const size_t n = B.n;
@@ -740,6 +761,69 @@ int check_ready(ccmg_solver* s)
 // ============================================================================
 // C ABI
 // ============================================================================
+namespace {
+
+template <int SF>
+void launch_deposit_sub(ccmg_solver* s, int n, const double* c, const double* r, const double* q, double eps, int mode,
+                        double* f, double* w)
+{
+    const LevelBuf& B = s->lv[0];
+    hipLaunchKernelGGL((k_deposit_sub<SF>), dim3(n), dim3(kSphereThreads), 0, s->stream, c, r, q, eps, s->h, B.nx,
+                       B.ny, B.nz, mode, f, w);
+}
+
+template <int SF>
+void launch_dq_sub(ccmg_solver* s, int n, const double* c, const double* r, double eps, int mode, const double* lam,
+                   double* dq)
+{
+    const LevelBuf& B = s->lv[0];
+    hipLaunchKernelGGL((k_dq_sub<SF>), dim3(n), dim3(kSphereThreads), 0, s->stream, c, r, eps, s->h, B.nx, B.ny,
+                       B.nz, mode, lam, dq);
+}
+
+template <template <int> class K, typename... A>
+bool by_subsample(int sf, A... a)
+{
+    switch (sf) {
+    case 1: K<1>::run(a...); return true;
+    case 2: K<2>::run(a...); return true;
+    case 3: K<3>::run(a...); return true;
+    case 4: K<4>::run(a...); return true;
+    case 5: K<5>::run(a...); return true;
+    case 6: K<6>::run(a...); return true;
+    case 7: K<7>::run(a...); return true;
+    case 8: K<8>::run(a...); return true;
+    default: return false;
+    }
+}
+
+template <int SF>
+struct DepositSub {
+    template <typename... A>
+    static void run(A... a) { launch_deposit_sub<SF>(a...); }
+};
+
+template <int SF>
+struct DqSub {
+    template <typename... A>
+    static void run(A... a) { launch_dq_sub<SF>(a...); }
+};
+
+int check_spheres(ccmg_solver* s, int n, const double* c, const double* r, int subsample, int mode)
+{
+    if (n < 0) return fail(s, CCMG_E_ARG, "negative sphere count");
+    if (subsample < 1 || subsample > CCMG_MAX_SUBSAMPLE)
+        return fail(s, CCMG_E_ARG, "subsample must be in 1..%d", CCMG_MAX_SUBSAMPLE);
+    if (mode != CCMG_CHARGE_SPREAD && mode != CCMG_CHARGE_VOLUME) return fail(s, CCMG_E_ARG, "unknown charge mode");
+    if (n > 0) {
+        NEED_DEV(s, c, "d_centers");
+        NEED_DEV(s, r, "d_radii");
+    }
+    return CCMG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void ccmg_default_options(ccmg_options* o)
@@ -893,6 +977,59 @@ int ccmg_deposit_charges(ccmg_solver* s, int n, const double* d_centers, const d
                            B.nx, B.ny, B.nz, d_f, d_counts);
     }
     LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+int ccmg_deposit_charges_sub(ccmg_solver* s, int n, const double* d_centers, const double* d_radii, const double* d_q,
+                             double eps, int subsample, int mode, double* d_f, double* d_weights)
+{
+    if (!s) return CCMG_E_ARG;
+    s->err.clear();
+    int rc = check_spheres(s, n, d_centers, d_radii, subsample, mode);
+    if (rc) return rc;
+    if (!(eps > 0.0)) return fail(s, CCMG_E_ARG, "eps must be positive");
+    NEED_DEV(s, d_f, "d_f");
+    const LevelBuf& B = s->lv[0];
+    hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(B.n)), dim3(256), 0, s->stream, d_f, B.n, 0.0);
+    if (n > 0) {
+        NEED_DEV(s, d_q, "d_q");
+        if (d_weights) NEED_DEV(s, d_weights, "d_weights");
+        by_subsample<DepositSub>(subsample, s, n, d_centers, d_radii, d_q, eps, mode, d_f, d_weights);
+    }
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+int ccmg_charge_gradient(ccmg_solver* s, int n, const double* d_centers, const double* d_radii, double eps,
+                         int subsample, int mode, const double* d_lambda, double* d_dq)
+{
+    if (!s) return CCMG_E_ARG;
+    s->err.clear();
+    int rc = check_spheres(s, n, d_centers, d_radii, subsample, mode);
+    if (rc) return rc;
+    if (!(eps > 0.0)) return fail(s, CCMG_E_ARG, "eps must be positive");
+    if (n == 0) return CCMG_OK;
+    NEED_DEV(s, d_lambda, "d_lambda");
+    NEED_DEV(s, d_dq, "d_dq");
+    by_subsample<DqSub>(subsample, s, n, d_centers, d_radii, eps, mode, d_lambda, d_dq);
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+int ccmg_set_face_values(ccmg_solver* s, int face, const double* d_values)
+{
+    if (!s) return CCMG_E_ARG;
+    s->err.clear();
+    if (face < 0 || face > 5) return fail(s, CCMG_E_ARG, "face must be in 0..5");
+    if (!s->ws) return fail(s, CCMG_E_STATE, "no workspace set (ccmg_set_workspace)");
+    if (d_values == nullptr) {
+        s->face_on[face] = false;
+        return CCMG_OK;
+    }
+    NEED_DEV(s, d_values, "d_values");
+    HIPCHK(s, hipMemcpyAsync(s->face_vals[face], d_values, sizeof(double) * face_cells(s, face),
+                             hipMemcpyDeviceToDevice, s->stream));
+    s->face_on[face] = true;
     return CCMG_OK;
 }
 

@@ -1067,23 +1067,44 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomParams<T>
 
 // Finest right-hand side with the boundary terms folded in (Sec. 2.4, Sec. 5.3):
 // b-tilde = h^2 (f + sum over the cell's boundary faces of term_f), where
-// term_f = 2 g_d / h^2 (Dirichlet) or g_n / h (Neumann).
-__global__ void k_fold(const double* f, double* bt, int nx, int ny, int nz, double h2,
-                       double t0, double t1, double t2, double t3, double t4, double t5, Ctl* ctl)
+// term_f = 2 g_d / h^2 (Dirichlet) or g_n / h (Neumann), faces added in the
+// order x-, x+, y-, y+, z-, z+.  A face with a value array takes g per
+// boundary cell: x faces [nz][ny], y faces [nz][nx], z faces [ny][nx].
+struct FoldParams {
+    const double* f;
+    double* bt;
+    int nx, ny, nz;
+    double h, h2;
+    double t[6];              // constant terms of faces without a value array
+    const double* face[6];    // per-cell boundary values, or null
+    int dirichlet[6];
+};
+
+__device__ __forceinline__ double fold_term(const FoldParams& P, int fc, size_t at)
 {
+#pragma clang fp contract(off)
+    if (P.face[fc] == nullptr) return P.t[fc];
+    const double g = P.face[fc][at];
+    return P.dirichlet[fc] ? 2.0 * g / (P.h * P.h) : g / P.h;
+}
+
+__global__ void k_fold(FoldParams P)
+{
+#pragma clang fp contract(off)
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
     const size_t n = (size_t)nx * ny * nz;
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(c % nx);
         const int j = (int)((c / nx) % ny);
         const int k = (int)(c / ((size_t)nx * ny));
-        double v = f[c];
-        if (i == 0) v += t0;
-        if (i == nx - 1) v += t1;
-        if (j == 0) v += t2;
-        if (j == ny - 1) v += t3;
-        if (k == 0) v += t4;
-        if (k == nz - 1) v += t5;
-        bt[c] = v * h2;
+        double v = P.f[c];
+        if (i == 0) v += fold_term(P, 0, (size_t)k * ny + j);
+        if (i == nx - 1) v += fold_term(P, 1, (size_t)k * ny + j);
+        if (j == 0) v += fold_term(P, 2, (size_t)k * nx + i);
+        if (j == ny - 1) v += fold_term(P, 3, (size_t)k * nx + i);
+        if (k == 0) v += fold_term(P, 4, (size_t)j * nx + i);
+        if (k == nz - 1) v += fold_term(P, 5, (size_t)j * nx + i);
+        P.bt[c] = v * P.h2;
     }
 }
 
@@ -1237,6 +1258,117 @@ __global__ __launch_bounds__(kSphereThreads) void k_dq(const double* centers, co
 #pragma clang fp contract(off)
         dq[s] = ns > 0.0 ? sum / (eps * ns * h * h * h) : 0.0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Sub-sampled deposition (Sec. 2.4, "Subsampling"): the overlap ratio of a
+// cell is the fraction of its SF^3 equidistant sub-cell centres
+// ((i + (a + 1/2)/SF) h, ...) inside the closed ball.  The distance test is
+// (dx*dx + dy*dy) + dz*dz <= R*R, uncontracted, so every implementation of
+// the definition counts the same sub-cells.
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846;
+
+template <int SF>
+__device__ __forceinline__ int sub_cells_in_ball(int i, int j, int k, double h, double cx, double cy, double cz,
+                                                 double R2)
+{
+#pragma clang fp contract(off)
+    double dx2[SF], dy2[SF], dz2[SF];
+#pragma unroll
+    for (int a = 0; a < SF; ++a) {
+        const double o = ((double)a + 0.5) / (double)SF;
+        const double dx = ((double)i + o) * h - cx;
+        const double dy = ((double)j + o) * h - cy;
+        const double dz = ((double)k + o) * h - cz;
+        dx2[a] = dx * dx;
+        dy2[a] = dy * dy;
+        dz2[a] = dz * dz;
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int c = 0; c < SF; ++c)
+#pragma unroll
+        for (int b = 0; b < SF; ++b)
+#pragma unroll
+            for (int a = 0; a < SF; ++a) cnt += (dx2[a] + dy2[b] + dz2[c] <= R2) ? 1 : 0;
+    return cnt;
+}
+
+// charge normalisation of sphere s: spread (q W h^3 = q: the charge is kept)
+// or volume (the paper's density q / (4/3 pi R^3) times the overlap ratio)
+__device__ __forceinline__ double sphere_norm(int mode, double eps, double W, double R, double h)
+{
+#pragma clang fp contract(off)
+    return mode == 0 ? eps * W * h * h * h : eps * ((4.0 / 3.0) * kPi * R * R * R);
+}
+
+// one workgroup per sphere: total sub-cell count W_s SF^3 (an exact integer
+// sum), then q_s w_c / norm_s added to every overlapped cell
+template <int SF>
+__global__ __launch_bounds__(kSphereThreads) void k_deposit_sub(const double* centers, const double* radii,
+                                                               const double* q, double eps, double h, int nx,
+                                                               int ny, int nz, int mode, double* f,
+                                                               double* weights)
+{
+#pragma clang fp contract(off)
+    const int s = blockIdx.x;
+    const double cx = centers[3 * s], cy = centers[3 * s + 1], cz = centers[3 * s + 2], R = radii[s];
+    const double R2 = R * R;
+    Box B;
+    ball_box(cx, R, h, nx, B.i0, B.i1);
+    ball_box(cy, R, h, ny, B.j0, B.j1);
+    ball_box(cz, R, h, nz, B.k0, B.k1);
+    const int bx = B.i1 - B.i0 + 1, by = B.j1 - B.j0 + 1, bz = B.k1 - B.k0 + 1;
+    const long long nbox = (bx > 0 && by > 0 && bz > 0) ? (long long)bx * by * bz : 0;
+    double cnt = 0.0;
+    for (long long c = threadIdx.x; c < nbox; c += kSphereThreads) {
+        const int i = B.i0 + (int)(c % bx), j = B.j0 + (int)((c / bx) % by), k = B.k0 + (int)(c / ((long long)bx * by));
+        cnt += (double)sub_cells_in_ball<SF>(i, j, k, h, cx, cy, cz, R2);
+    }
+    const double W = block_sum_d<kSphereThreads>(cnt) / (double)(SF * SF * SF);
+    if (threadIdx.x == 0 && weights != nullptr) weights[s] = W;
+    if (W == 0.0) return;
+    const double norm = sphere_norm(mode, eps, W, R, h);
+    const double qs = q[s];
+    for (long long c = threadIdx.x; c < nbox; c += kSphereThreads) {
+        const int i = B.i0 + (int)(c % bx), j = B.j0 + (int)((c / bx) % by), k = B.k0 + (int)(c / ((long long)bx * by));
+        const int m = sub_cells_in_ball<SF>(i, j, k, h, cx, cy, cz, R2);
+        if (m > 0) {
+            const double w = (double)m / (double)(SF * SF * SF);
+            atomicAdd(&f[((size_t)k * ny + j) * nx + i], qs * w / norm);
+        }
+    }
+}
+
+// dL/dq_s = sum_c lambda_c w_c / norm_s for the sub-sampled deposition
+template <int SF>
+__global__ __launch_bounds__(kSphereThreads) void k_dq_sub(const double* centers, const double* radii, double eps,
+                                                          double h, int nx, int ny, int nz, int mode,
+                                                          const double* lam, double* dq)
+{
+#pragma clang fp contract(off)
+    const int s = blockIdx.x;
+    const double cx = centers[3 * s], cy = centers[3 * s + 1], cz = centers[3 * s + 2], R = radii[s];
+    const double R2 = R * R;
+    Box B;
+    ball_box(cx, R, h, nx, B.i0, B.i1);
+    ball_box(cy, R, h, ny, B.j0, B.j1);
+    ball_box(cz, R, h, nz, B.k0, B.k1);
+    const int bx = B.i1 - B.i0 + 1, by = B.j1 - B.j0 + 1, bz = B.k1 - B.k0 + 1;
+    const long long nbox = (bx > 0 && by > 0 && bz > 0) ? (long long)bx * by * bz : 0;
+    double cnt = 0.0, acc = 0.0;
+    for (long long c = threadIdx.x; c < nbox; c += kSphereThreads) {
+        const int i = B.i0 + (int)(c % bx), j = B.j0 + (int)((c / bx) % by), k = B.k0 + (int)(c / ((long long)bx * by));
+        const int m = sub_cells_in_ball<SF>(i, j, k, h, cx, cy, cz, R2);
+        if (m > 0) {
+            cnt += (double)m;
+            acc += lam[((size_t)k * ny + j) * nx + i] * ((double)m / (double)(SF * SF * SF));
+        }
+    }
+    const double W = block_sum_d<kSphereThreads>(cnt) / (double)(SF * SF * SF);
+    const double sum = block_sum_d<kSphereThreads>(acc);
+    if (threadIdx.x == 0) dq[s] = (mode == 0 && W == 0.0) ? 0.0 : sum / sphere_norm(mode, eps, W, R, h);
 }
 
 }  // namespace ccmg

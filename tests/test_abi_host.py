@@ -98,6 +98,21 @@ def test_calls_without_workspace_fail_cleanly():
     assert L.ccmg_solve(hd, None, None, 1e-10, 10, None) == pkg.E_STATE
     assert L.ccmg_vcycle(hd, None, None, None) == pkg.E_STATE
     assert b"workspace" in L.ccmg_last_error(hd)
+    assert L.ccmg_set_face_values(hd, 0, None) == pkg.E_STATE
+    L.ccmg_destroy(hd)
+
+
+@pytest.mark.parametrize("subsample,mode", [(0, 0), (9, 0), (2, 2), (3, -1)])
+def test_subsampled_deposition_rejects_arguments(subsample, mode):
+    """Checked before any device access (n = 0 spheres)."""
+    L = pkg.lib()
+    rc, hd = create((32, 32, 32), ZD)
+    assert rc == 0
+    assert L.ccmg_deposit_charges_sub(hd, 0, None, None, None, 1.0, subsample, mode, None, None) == pkg.E_ARG
+    assert L.ccmg_charge_gradient(hd, 0, None, None, 1.0, subsample, mode, None, None) == pkg.E_ARG
+    assert L.ccmg_last_error(hd)
+    assert L.ccmg_charge_gradient(hd, -1, None, None, 1.0, 2, 0, None, None) == pkg.E_ARG
+    assert L.ccmg_set_face_values(hd, 7, None) == pkg.E_ARG
     L.ccmg_destroy(hd)
 
 

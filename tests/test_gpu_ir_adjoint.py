@@ -85,11 +85,14 @@ def test_dq_parity_and_autograd():
     assert np.abs(fr.grad.cpu().numpy() - lam_ref).max() <= 1e-12 * np.abs(lam_ref).max()
 
 
-def test_dq_matches_finite_differences_fixed_cycles():
-    """Central differences (step 1e-6) of L = sum w phi over sphere charges, with
-    the forward solves run for a fixed cycle count so that the discrete map
-    q -> phi is linear and smooth (its contraction makes the remainder negligible)."""
-    w = W.C4.scaled((64, 64, 64), levels=4, n_spheres=40)
+@pytest.mark.parametrize("shape,levels", [((64, 64, 64), 4), ((128, 128, 128), 5)])
+def test_dq_matches_finite_differences_fixed_cycles(shape, levels):
+    """Central differences (step 1e-6) of L = sum w phi over 16 seeded sphere
+    charges, with the forward solves run for a fixed cycle count so that the
+    discrete map q -> phi is linear (its contraction makes the remainder
+    negligible); the 128^3 case is the full gradient workload."""
+    w = W.C4 if shape == W.C4.shape else W.C4.scaled(shape, levels=levels, n_spheres=40)
+    log_case("fd", shape)
     sph = W.workload_spheres(w)
     s = solver(w.shape, w.levels, w.kinds, w.values, h=w.h)
     wts = to_dev(W.loss_weights(w))
@@ -103,6 +106,7 @@ def test_dq_matches_finite_differences_fixed_cycles():
         return float((phi * wts).sum())
     step = w.extra["fd_step"]
     dq = dq.cpu().numpy()
+    assert len(idx) == 16
     for i in idx:
         qp, qm = sph.charges.copy(), sph.charges.copy()
         qp[i] += step
@@ -123,6 +127,30 @@ def test_fp32_ir_gradient_matches_fp64():
         out[prec] = dq.cpu().numpy()
     rel = np.abs(out[pkg.FP32_IR] - out[pkg.FP64]).max() / np.abs(out[pkg.FP64]).max()
     assert rel <= 1e-6
+
+
+def test_channel_forward_and_adjoint_fp32_ir_vs_fp64():
+    """Full 1024x256x256 channel: FP32-IR forward and adjoint solves agree with
+    the FP64 solver (both to 1e-10), and the charge gradient agrees to 1e-6."""
+    w = W.C5
+    log_case("channel fwd+adj")
+    sph = W.workload_spheres(w)
+    c, r, q = (to_dev(a) for a in (sph.centers, sph.radii, sph.charges))
+    wts = torch.tensor(np.random.default_rng(5005).standard_normal((256, 256, 1024)), device=DEV)
+    out = {}
+    for prec in (pkg.FP64, pkg.FP32_IR):
+        s = solver(w.shape, w.levels, w.kinds, w.values, h=w.h, precision=prec)
+        f = s.deposit(c, r, q)
+        phi, st = s.solve(f, rtol=1e-10)
+        lam, dq, _, ast = s.adjoint(wts, c, r, rtol=1e-10)
+        assert st.rel_res < 1e-10 and ast.rel_res < 1e-10
+        out[prec] = (phi.cpu().numpy(), dq.cpu().numpy())
+        del s, phi, lam, f
+        torch.cuda.empty_cache()
+    p64, g64 = out[pkg.FP64]
+    p32, g32 = out[pkg.FP32_IR]
+    assert np.abs(p32 - p64).max() <= 1e-6 * np.abs(p64).max()
+    assert np.abs(g32 - g64).max() <= 1e-6 * np.abs(g64).max()
 
 
 # ---- error paths, forced from the host ------------------------------------
