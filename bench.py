@@ -121,6 +121,54 @@ def cpu_baseline(w: W.Workload, sph, budget_s: float = 12.0):
             "seconds_per_solve": per}, phi
 
 
+def timestep_scene(dev, steps: int):
+    """The paper's per-node time-step use of the solver: 256 x 512 x 256 cells,
+    3456 moving spheres deposited with sub-sampling factor 2 (volume
+    normalisation), 5 warm V(3,3)-cycles at the first step and 1 per later
+    step, the residual norm of every step written on the device.  One step =
+    deposition + fold + cycle(s); inputs (all sphere positions) resident in HBM."""
+    w = W.SCENE
+    sph = W.scene_spheres(w)
+    warm = 3
+    traj = torch.tensor(W.scene_trajectory(w, max(steps, warm)), device=dev)
+    r = torch.tensor(sph.radii, device=dev)
+    q = torch.tensor(sph.charges, device=dev)
+    s = make_solver(w, dev)
+    f = s.zeros()
+    phi = s.zeros()
+    rels = torch.zeros(max(steps, warm), dtype=torch.float64, device=dev)
+    sf, first, per = w.extra["subsample"], w.extra["first_cycles"], w.extra["cycles"]
+
+    def run(n):
+        for t in range(n):
+            s.deposit(traj[t], r, q, w.eps, out=f, subsample=sf, mode=pkg.VOLUME)
+            s.vcycles(phi, f, first if t == 0 else per, rels[t:t + 1])
+
+    run(warm)
+    torch.cuda.synchronize()
+    phi.zero_()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    run(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    secs = ev0.elapsed_time(ev1) / 1e3
+    cycles = first + (steps - 1) * per
+    rel = rels[:steps].cpu().numpy()
+    return {"workload": w.name, "cells": list(w.shape), "spheres": sph.n, "steps": steps, "cycles": cycles,
+            "cycle": f"V({w.nu1},{w.nu2})", "levels": s.levels, "coarsest": list(s.level_dims(s.levels - 1)),
+            "subsample": sf, "deposition": "volume (q/V per overlapped fraction)", "precision": "fp64",
+            "ms_per_step": secs / steps * 1e3, "mlups": w.cells * steps / secs / 1e6,
+            "cell_cycles_per_s": w.cells * cycles / secs,
+            "rel_res_step0": float(rel[0]), "rel_res_last": float(rel[-1]),
+            "rel_res_max_later_steps": float(rel[1:].max()) if steps > 1 else None,
+            "paper_context": {"mlups_per_node": 91.8, "hardware": "1 SuperMUC node (2x 8-core Xeon E5-2680)",
+                              "note": "same scene size and cycle schedule; other machine: context, not a target"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +179,8 @@ def main():
     ap.add_argument("--no-ir", action="store_true", help="skip the FP32-IR comparison")
     ap.add_argument("--fuse", type=int, default=2)
     ap.add_argument("--inner", type=int, default=2)
+    ap.add_argument("--no-scene", action="store_true", help="skip the time-step scene")
+    ap.add_argument("--scene-steps", type=int, default=240)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -225,6 +275,13 @@ def main():
         log(f"fp32-ir: {t32 / args.steps * 1e3:.3f} ms/step, {st32.cycles} outer, rel {rel64:.2e}, "
             f"max|dphi| vs fp64 {diff:.2e}")
         del s32, phi32
+
+    if not args.no_scene:
+        del s
+        torch.cuda.empty_cache()
+        out["timestep_scene"] = ts = timestep_scene(dev, args.scene_steps)
+        log(f"time-step scene: {ts['ms_per_step']:.3f} ms/step, {ts['mlups']:.0f} MLUPS, "
+            f"rel res last {ts['rel_res_last']:.2e}, max later {ts['rel_res_max_later_steps']:.2e}")
 
     if not args.no_cpu:
         base, phi_cpu = cpu_baseline(w, sph)

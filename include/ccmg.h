@@ -179,6 +179,16 @@ int ccmg_set_face_values(ccmg_solver* s, int face, const double* d_values);
  * residual ||b - A phi|| / ||b|| after the cycle (synchronises). */
 int ccmg_vcycle(ccmg_solver* s, double* d_phi, const double* d_f, double* rel_res_out);
 
+/* Warm-started cycles for a time-step loop (Sec. 8.1 runs five V(3,3)-cycles
+ * at the first time step and one per later step from the previous
+ * solution): `ncycles` cycles (FP64) or refinement steps (FP32-IR) on d_phi
+ * (in/out) for the right-hand side d_f, all enqueued without waiting.
+ * d_rel_out (nullable, one double of device memory) receives the relative
+ * residual ||b - A phi|| / ||b|| after the last cycle (NaN if it is not
+ * finite), written on the stream; nothing is synchronised.  ncycles in
+ * 0..CCMG_MAX_CYCLES (0: nothing is enqueued). */
+int ccmg_vcycles(ccmg_solver* s, double* d_phi, const double* d_f, int ncycles, double* d_rel_out);
+
 /* Multigrid solve (Alg. 1): d_phi holds the initial guess on entry (it is not
  * zeroed) and the solution on return.  Cycles (FP64) or refinement steps
  * (FP32-IR) are performed while ||b - A phi|| / ||b|| >= rtol, at most

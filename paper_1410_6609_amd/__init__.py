@@ -107,6 +107,7 @@ _SIGS = {
                              ctypes.c_int),
     "ccmg_set_face_values": ([_VP, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_vcycle": ([_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "ccmg_vcycles": ([_VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_solve": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
     "ccmg_adjoint_solve": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_double, _VP, _VP,
                             ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
@@ -295,6 +296,20 @@ class Solver:
         self._bind_stream()
         self._check(lib().ccmg_vcycle(self._h, _ptr(phi), _ptr(f), ctypes.byref(out) if norm else None))
         return out.value if norm else None
+
+    def vcycles(self, phi: torch.Tensor, f: torch.Tensor, ncycles: int,
+                rel_out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """`ncycles` warm-started cycles on phi, enqueued without waiting;
+        rel_out (a float64 device tensor of one element, or None) receives the
+        relative residual after the last cycle."""
+        phi = self._field(phi, "phi")
+        f = self._field(f, "f")
+        if rel_out is not None and (rel_out.device != self.device or rel_out.dtype != torch.float64
+                                    or rel_out.numel() != 1):
+            raise ValueError("rel_out must be one float64 element on the solver's device")
+        self._bind_stream()
+        self._check(lib().ccmg_vcycles(self._h, _ptr(phi), _ptr(f), int(ncycles), _ptr(rel_out)))
+        return phi
 
     def adjoint(self, g: torch.Tensor, centers=None, radii=None, eps: float = 1.0, rtol: float = 1e-10,
                 max_cycles: int = 100, want_drho: bool = False, lam: Optional[torch.Tensor] = None,

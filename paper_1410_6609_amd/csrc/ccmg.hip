@@ -1033,6 +1033,39 @@ int ccmg_set_face_values(ccmg_solver* s, int face, const double* d_values)
     return CCMG_OK;
 }
 
+namespace {
+
+// one cycle (FP64) or one refinement step (FP32-IR) on the folded RHS; with
+// `norm` the finest residual norm is reduced into the control block
+int enqueue_cycle(ccmg_solver* s, double* d_phi, bool norm)
+{
+    int rc;
+    if (s->opt.precision == CCMG_FP64) return enqueue_vcycle<double>(s, fp64_ptrs(s, d_phi), false, norm ? 1 : 0);
+    // FP32 cycles on the scaled residual, FP64 update (the update pass also
+    // reduces the next residual norm)
+    if ((rc = enqueue_norm(s, d_phi, FIN_INIT, RES_NORM, nullptr, nullptr, 0))) return rc;
+    if ((rc = enqueue_norm(s, d_phi, FIN_CYCLE, RES_NORM_R32, nullptr, s->lv[0].b32, 0))) return rc;
+    const LevelPtrs<float> H = fp32_ptrs(s);
+    for (int m = 0; m < s->opt.ir_inner_cycles; ++m)
+        if ((rc = enqueue_vcycle<float>(s, H, m == 0, 0))) return rc;
+    PassParams<double> P = base_params<double>(s, 0);
+    P.phi_in = d_phi;
+    P.phi_out = s->lv[0].tmp;
+    P.b = s->lv[0].b;
+    P.corr = s->lv[0].phi32;
+    P.r32_out = s->lv[0].b32;
+    P.fin = FIN_CYCLE;
+    P.cycle = 1;
+    if (!dispatch<double>(0, LOAD_CORR, RES_NORM_R32, P, s->stream)) return fail(s, CCMG_E_ARG, "IR pass");
+    const size_t n = s->lv[0].n;
+    hipLaunchKernelGGL((k_copy<double>), dim3(grid1d(n)), dim3(256), 0, s->stream, (const double*)s->lv[0].tmp, d_phi,
+                       n, (const Ctl*)nullptr);
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+}  // namespace
+
 int ccmg_vcycle(ccmg_solver* s, double* d_phi, const double* d_f, double* rel_res_out)
 {
     int rc = check_ready(s);
@@ -1042,36 +1075,32 @@ int ccmg_vcycle(ccmg_solver* s, double* d_phi, const double* d_f, double* rel_re
     NEED_DEV(s, d_f, "d_f");
     if ((rc = enqueue_ctl_init(s, -1.0))) return rc;
     if ((rc = enqueue_fold(s, d_f, false))) return rc;
-    if (s->opt.precision == CCMG_FP64) {
-        rc = enqueue_vcycle<double>(s, fp64_ptrs(s, d_phi), false, rel_res_out ? 1 : 0);
-        if (rc) return rc;
-    } else {
-        // one refinement step: FP32 cycles on the scaled residual, FP64 update
-        if ((rc = enqueue_norm(s, d_phi, FIN_INIT, RES_NORM, nullptr, nullptr, 0))) return rc;
-        if ((rc = enqueue_norm(s, d_phi, FIN_CYCLE, RES_NORM_R32, nullptr, s->lv[0].b32, 0))) return rc;
-        const LevelPtrs<float> H = fp32_ptrs(s);
-        for (int m = 0; m < s->opt.ir_inner_cycles; ++m)
-            if ((rc = enqueue_vcycle<float>(s, H, m == 0, 0))) return rc;
-        PassParams<double> P = base_params<double>(s, 0);
-        P.phi_in = d_phi;
-        P.phi_out = s->lv[0].tmp;
-        P.b = s->lv[0].b;
-        P.corr = s->lv[0].phi32;
-        P.r32_out = s->lv[0].b32;
-        P.fin = FIN_CYCLE;
-        P.cycle = 1;
-        if (!dispatch<double>(0, LOAD_CORR, RES_NORM_R32, P, s->stream)) return fail(s, CCMG_E_ARG, "IR pass");
-        const size_t n = s->lv[0].n;
-        hipLaunchKernelGGL((k_copy<double>), dim3(grid1d(n)), dim3(256), 0, s->stream, (const double*)s->lv[0].tmp,
-                           d_phi, n, (const Ctl*)nullptr);
-        LAUNCHCHK(s);
-    }
+    if ((rc = enqueue_cycle(s, d_phi, rel_res_out != nullptr))) return rc;
     if (rel_res_out) {
         CtlHead h;
         if ((rc = read_ctl(s, h, -1))) return rc;
         *rel_res_out = h.rel;
         if (h.status == -5) return fail(s, CCMG_E_NONFINITE, "residual is not finite");
     }
+    return CCMG_OK;
+}
+
+int ccmg_vcycles(ccmg_solver* s, double* d_phi, const double* d_f, int ncycles, double* d_rel_out)
+{
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    if (ncycles < 0 || ncycles > CCMG_MAX_CYCLES) return fail(s, CCMG_E_ARG, "ncycles out of range");
+    NEED_DEV(s, d_phi, "d_phi");
+    NEED_DEV(s, d_f, "d_f");
+    if (d_rel_out) NEED_DEV(s, d_rel_out, "d_rel_out");
+    if (ncycles == 0) return CCMG_OK;
+    if ((rc = enqueue_ctl_init(s, -1.0))) return rc;
+    if ((rc = enqueue_fold(s, d_f, false))) return rc;
+    for (int m = 0; m < ncycles; ++m)
+        if ((rc = enqueue_cycle(s, d_phi, d_rel_out != nullptr && m == ncycles - 1))) return rc;
+    if (d_rel_out)
+        HIPCHK(s, hipMemcpyAsync(d_rel_out, &s->ctl->rel, sizeof(double), hipMemcpyDeviceToDevice, s->stream));
     return CCMG_OK;
 }
 

@@ -99,6 +99,7 @@ def test_calls_without_workspace_fail_cleanly():
     assert L.ccmg_vcycle(hd, None, None, None) == pkg.E_STATE
     assert b"workspace" in L.ccmg_last_error(hd)
     assert L.ccmg_set_face_values(hd, 0, None) == pkg.E_STATE
+    assert L.ccmg_vcycles(hd, None, None, 1, None) == pkg.E_STATE
     L.ccmg_destroy(hd)
 
 

@@ -101,6 +101,29 @@ def test_vcycle_parity_per_cycle(case):
         assert abs(rel - hist[-1]) <= 1e-9 * hist[-1], (k, rel, hist[-1])
 
 
+@pytest.mark.parametrize("fuse", [1, 2])
+@pytest.mark.parametrize("nu", [(3, 3), (1, 1), (1, 3), (3, 2)])
+@pytest.mark.parametrize("case", [CASES[1], CASES[3]], ids=ids)
+def test_vcycle_parity_other_sweep_counts(case, nu, fuse):
+    """V(nu1,nu2) for the paper's V(3,3) and V(1,1) (Sec. 3, Sec. 8.1) and mixed
+    counts, split into one- and two-sweep passes."""
+    shape, levels, kinds, values = case
+    log_case("vcycle nu", shape, nu, fuse)
+    s = solver_for(shape, levels, kinds, values, nu1=nu[0], nu2=nu[1], fuse_sweeps=fuse)
+    h = 1.0 / shape[0]
+    f = rhs(shape, 7)
+    fd = to_dev(f)
+    phi = s.zeros()
+    b = oracle.fold(f, h, kinds, values)
+    ref = np.zeros_like(f)
+    for k in range(1, 4):
+        rel = s.vcycle(phi, fd)
+        ref, hist, _ = oracle.solve(b, h, kinds, levels, nu1=nu[0], nu2=nu[1], rtol=0.0, max_cycles=1, phi0=ref)
+        got = phi.cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), k
+        assert abs(rel - hist[-1]) <= 1e-9 * hist[-1], (k, rel, hist[-1])
+
+
 @pytest.mark.parametrize("case", CASES, ids=ids)
 def test_solve_parity(case):
     shape, levels, kinds, values = case

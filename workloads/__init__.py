@@ -109,6 +109,56 @@ C5 = Workload("c5_channel_1024x256x256", (1024, 256, 256), 1.0, _XK, _XV, levels
 
 ALL = {w.name: w for w in (C1, C2, C3, C4, C5)}
 
+# SI constants for the per-node scene
+EPS0 = 8.8541878128e-12        # vacuum permittivity, F/m
+E_CHARGE = 1.602176634e-19     # elementary charge, C
+
+# The paper's per-node time-step scene (parameters of the agglomeration
+# showcase, Sec. 7; single-node set-up of the scaling runs, Sec. 8.1):
+# 256 x 512 x 256 cells of 10 um (2 x 4 x 2 blocks of 128^3), in each block one
+# set of 6^3 spheres of radius 6 cells at 12-cell centre spacing, centred in the
+# block (3456 spheres); 8000 e per sphere, eps = 78.5 eps0; phi = -100 V at the
+# bottom plane (z = 0) and 0 V at the top plane, insulating (zero-Neumann)
+# sides; V(3,3) on 7 levels (coarsest 4 x 8 x 4), sub-sampling factor 2;
+# 5 cycles at the first time step, then 1 per step, 240 steps.  The spheres
+# drift by a seeded velocity per step (a common 0.004 cells/step towards the
+# bottom plus a uniform jitter of up to 0.004 cells/step per axis).
+_SK, _SV = _dirichlet_pair_axis(2, -100.0, 0.0)
+SCENE = Workload("scene_256x512x256", (256, 512, 256), 1e-5, _SK, _SV, levels=7, nu1=3, nu2=3,
+                 eps=78.5 * EPS0, n_spheres=3456, r_lo=6.0, r_hi=6.0, seed=1006,
+                 extra={"block": 128, "set": 6, "spacing": 12.0, "charge": 8000 * E_CHARGE, "subsample": 2,
+                        "steps": 240, "first_cycles": 5, "cycles": 1, "drift": 0.004})
+
+
+def scene_spheres(w: Workload) -> Spheres:
+    """Initial spheres of a time-step scene: one set^3 lattice per block, centred."""
+    b, m, d = w.extra["block"], w.extra["set"], w.extra["spacing"]
+    first = b / 2.0 - d * (m - 1) / 2.0
+    offs = first + d * np.arange(m)
+    nbx, nby, nbz = (n // b for n in w.shape)
+    cs = []
+    for bz in range(nbz):
+        for by in range(nby):
+            for bx in range(nbx):
+                for z in offs:
+                    for y in offs:
+                        for x in offs:
+                            cs.append((bx * b + x, by * b + y, bz * b + z))
+    c = np.asarray(cs, dtype=np.float64) * w.h
+    n = c.shape[0]
+    return Spheres(np.ascontiguousarray(c), np.full(n, w.r_lo * w.h), np.full(n, float(w.extra["charge"])))
+
+
+def scene_trajectory(w: Workload, steps: int) -> np.ndarray:
+    """Sphere centres for time steps 0..steps-1, [steps, n, 3], physical units."""
+    s0 = scene_spheres(w)
+    rng = np.random.default_rng(w.seed)
+    d = w.extra["drift"]
+    v = rng.uniform(-d, d, size=(s0.n, 3))
+    v[:, 2] -= d
+    t = np.arange(steps, dtype=np.float64)[:, None, None]
+    return np.ascontiguousarray(s0.centers[None] + t * v[None] * w.h)
+
 
 def cell_centers_1d(n: int, h: float) -> np.ndarray:
     return (np.arange(n, dtype=np.float64) + 0.5) * h
