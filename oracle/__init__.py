@@ -66,6 +66,9 @@ def lib() -> ctypes.CDLL:
                                ctypes.POINTER(ctypes.c_void_p), dp, dp], None),
             "or_deposit_sub": ([I, I, I, D, I, dp, dp, dp, D, I, I, dp, dp], None),
             "or_dq_sub": ([I, I, I, D, I, dp, dp, D, I, I, dp, dp], None),
+            "or_gradient": ([I, I, I, D, ip, dp, ctypes.POINTER(ctypes.c_void_p), dp, dp], None),
+            "or_coulomb": ([I, I, I, D, ip, dp, ctypes.POINTER(ctypes.c_void_p), dp, I, dp, dp, dp, I, I, dp],
+                           None),
             "or_solve": ([I, I, I, D, ip, I, I, I, D, D, I, dp, dp, D, I, dp, ip], I),
             "or_solve_ir": ([I, I, I, D, ip, I, I, I, D, D, I, I, dp, dp, D, I, dp, ip], I),
         }
@@ -187,6 +190,38 @@ def fold_field(f, h, kinds, values, faces) -> np.ndarray:
     vals = (ctypes.c_double * 6)(*[float(v) for v in values])
     lib().or_fold_field(nx, ny, nz, h, _kinds(kinds), vals, ptrs, _dp(f), _dp(b))
     return b
+
+
+def _faces(shape, faces):
+    nx, ny, nz = shape
+    shapes = [(nz, ny)] * 2 + [(nz, nx)] * 2 + [(ny, nx)] * 2
+    faces = faces if faces is not None else [None] * 6
+    keep = [None if a is None else _f64(a).reshape(shapes[i]) for i, a in enumerate(faces)]
+    return keep, (ctypes.c_void_p * 6)(*[None if a is None else a.ctypes.data for a in keep])
+
+
+def gradient(phi, h, kinds, values, faces=None) -> np.ndarray:
+    """[3, nz, ny, nx]: D3Q19 gradient inside, D3Q7 with boundary ghosts on the boundary layer."""
+    phi = _f64(phi)
+    nx, ny, nz = _shape(phi)
+    out = np.empty((3, nz, ny, nx))
+    keep, ptrs = _faces((nx, ny, nz), faces)
+    vals = (ctypes.c_double * 6)(*[float(v) for v in values])
+    lib().or_gradient(nx, ny, nz, h, _kinds(kinds), vals, ptrs, _dp(phi), _dp(out))
+    return out
+
+
+def coulomb(phi, h, kinds, values, centers, radii, q, subsample: int = 1, mode: int = 0, faces=None) -> np.ndarray:
+    """Electrostatic force per sphere, [n, 3]."""
+    phi = _f64(phi)
+    nx, ny, nz = _shape(phi)
+    centers, radii, q = _f64(centers).reshape(-1, 3), _f64(radii), _f64(q)
+    out = np.zeros((radii.shape[0], 3))
+    keep, ptrs = _faces((nx, ny, nz), faces)
+    vals = (ctypes.c_double * 6)(*[float(v) for v in values])
+    lib().or_coulomb(nx, ny, nz, h, _kinds(kinds), vals, ptrs, _dp(phi), radii.shape[0], _dp(centers), _dp(radii),
+                     _dp(q), subsample, mode, _dp(out))
+    return out
 
 
 def deposit(shape, h, centers, radii, q, eps: float = 1.0):

@@ -583,6 +583,121 @@ void or_dq_sub(int nx, int ny, int nz, double h, int n, const double* centers, c
     }
 }
 
+/* ---- electrostatic force on the spheres (Sec. 2.4, "Coulomb force") ------- */
+
+/* Potential at (i,j,k), or the ghost value the boundary treatment implies
+ * when the cell lies one layer outside the domain across one face (Sec. 2.4:
+ * Dirichlet extrapolates phi_0 = 2 g - phi_1, Neumann takes
+ * phi_0 - phi_1 = h g_n with g_n the outward normal derivative).  The face
+ * value comes from face[fc] (per cell) when given, else values[fc]. */
+static double phi_or_ghost(const or_level* L, const double* phi, const int* kinds, const double* values,
+                           const double* const* face, double h, int i, int j, int k)
+{
+    int fc = -1, ii = i, jj = j, kk = k;
+    if (i < 0)             { fc = 0; ii = 0; }
+    else if (i >= L->nx)   { fc = 1; ii = L->nx - 1; }
+    else if (j < 0)        { fc = 2; jj = 0; }
+    else if (j >= L->ny)   { fc = 3; jj = L->ny - 1; }
+    else if (k < 0)        { fc = 4; kk = 0; }
+    else if (k >= L->nz)   { fc = 5; kk = L->nz - 1; }
+    const double in = phi[IDX(L, ii, jj, kk)];
+    if (fc < 0) return in;
+    double g;
+    if (face && face[fc]) {
+        const size_t at = fc < 2 ? (size_t)kk * L->ny + jj : fc < 4 ? (size_t)kk * L->nx + ii : (size_t)jj * L->nx + ii;
+        g = face[fc][at];
+    } else {
+        g = values[fc];
+    }
+    return kinds[fc] == OR_DIRICHLET ? 2.0 * g - in : in + h * g;
+}
+
+/* Gradient of phi at cell (i,j,k), second order: the isotropic D3Q19 lattice
+ * gradient grad = (1/w_1) sum_q w_q phi(x + h c_q) c_q / h over the 18
+ * non-rest directions (w_1 = 1/3 the rest weight, w = 1/18 along the axes,
+ * 1/36 along the face diagonals) where all 18 neighbours are inside the
+ * domain; elsewhere the D3Q7 central differences with the boundary ghost
+ * values. */
+static void gradient_at(const or_level* L, const double* phi, const int* kinds, const double* values,
+                        const double* const* face, double h, int i, int j, int k, double g[3])
+{
+    const int inner = i > 0 && i < L->nx - 1 && j > 0 && j < L->ny - 1 && k > 0 && k < L->nz - 1;
+    g[0] = g[1] = g[2] = 0.0;
+    if (inner) {
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int nnz = (dx != 0) + (dy != 0) + (dz != 0);
+                    if (nnz == 0 || nnz == 3) continue;   /* rest and cube-corner directions are not in D3Q19 */
+                    const double w = nnz == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
+                    const double v = phi[IDX(L, i + dx, j + dy, k + dz)];
+                    g[0] += w * v * (double)dx;
+                    g[1] += w * v * (double)dy;
+                    g[2] += w * v * (double)dz;
+                }
+        for (int a = 0; a < 3; ++a) g[a] = 3.0 * g[a] / h;
+        return;
+    }
+    g[0] = (phi_or_ghost(L, phi, kinds, values, face, h, i + 1, j, k) -
+            phi_or_ghost(L, phi, kinds, values, face, h, i - 1, j, k)) / (2.0 * h);
+    g[1] = (phi_or_ghost(L, phi, kinds, values, face, h, i, j + 1, k) -
+            phi_or_ghost(L, phi, kinds, values, face, h, i, j - 1, k)) / (2.0 * h);
+    g[2] = (phi_or_ghost(L, phi, kinds, values, face, h, i, j, k + 1) -
+            phi_or_ghost(L, phi, kinds, values, face, h, i, j, k - 1)) / (2.0 * h);
+}
+
+void or_gradient(int nx, int ny, int nz, double h, const int* kinds, const double* values,
+                 const double* const* face, const double* phi, double* grad /* [3][nz][ny][nx] */)
+{
+    const or_level L = make_level(nx, ny, nz, h, 0, kinds);
+    const size_t n = or_cells(&L);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double g[3];
+                gradient_at(&L, phi, kinds, values, face, h, i, j, k, g);
+                const size_t c = IDX(&L, i, j, k);
+                grad[c] = g[0];
+                grad[n + c] = g[1];
+                grad[2 * n + c] = g[2];
+            }
+}
+
+/* F_s = -h^3 sum_b grad(phi)(x_b) rho_s(x_b) (Eq. ElectrostatForce), with the
+ * sphere's own charge density of the sub-sampled deposition:
+ * rho_s = q_s w_{s,b} / (W_s h^3) (mode 0) or q_s w_{s,b} / (4/3 pi R^3)
+ * (mode 1).  force[3s..3s+2] = F_s; 0 for a sphere covering no sub-cell. */
+void or_coulomb(int nx, int ny, int nz, double h, const int* kinds, const double* values,
+                const double* const* face, const double* phi, int n, const double* centers, const double* radii,
+                const double* q, int sf, int mode, double* force)
+{
+    const or_level L = make_level(nx, ny, nz, h, 0, kinds);
+    for (int s = 0; s < n; ++s) {
+        const double* c = centers + 3 * (size_t)s;
+        const double R = radii[s];
+        double* F = force + 3 * (size_t)s;
+        F[0] = F[1] = F[2] = 0.0;
+        const double W = sphere_weight(nx, ny, nz, h, c, R, sf);
+        if (W == 0.0) continue;
+        const double norm = sphere_norm(mode, 1.0, W, R, h);
+        int ilo, ihi, jlo, jhi, klo, khi;
+        axis_range(c[0], R, h, nx, &ilo, &ihi);
+        axis_range(c[1], R, h, ny, &jlo, &jhi);
+        axis_range(c[2], R, h, nz, &klo, &khi);
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int k = klo; k <= khi; ++k)
+            for (int j = jlo; j <= jhi; ++j)
+                for (int i = ilo; i <= ihi; ++i) {
+                    const double w = cell_ratio(i, j, k, sf, h, c, R);
+                    if (w == 0.0) continue;
+                    double g[3];
+                    gradient_at(&L, phi, kinds, values, face, h, i, j, k, g);
+                    for (int a = 0; a < 3; ++a) acc[a] += g[a] * w;
+                }
+        for (int a = 0; a < 3; ++a) F[a] = -(h * h * h) * acc[a] * q[s] / norm;
+    }
+}
+
 /* Multigrid solve (Alg. 1): with rho_k = ||b - A phi_k||_2 / ||b||_2, perform
  * V-cycles while rho_k >= rtol, at most max_cycles.  b is the folded finest
  * right-hand side; phi holds the initial guess on entry.  hist[0..cycles]
