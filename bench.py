@@ -125,8 +125,9 @@ def timestep_scene(dev, steps: int):
     """The paper's per-node time-step use of the solver: 256 x 512 x 256 cells,
     3456 moving spheres deposited with sub-sampling factor 2 (volume
     normalisation), 5 warm V(3,3)-cycles at the first step and 1 per later
-    step, the residual norm of every step written on the device.  One step =
-    deposition + fold + cycle(s); inputs (all sphere positions) resident in HBM."""
+    step, the residual norm of every step written on the device, then the
+    electrostatic force on every sphere.  One step = deposition + fold +
+    cycle(s) + force; inputs (all sphere positions) resident in HBM."""
     w = W.SCENE
     sph = W.scene_spheres(w)
     warm = 3
@@ -137,12 +138,14 @@ def timestep_scene(dev, steps: int):
     f = s.zeros()
     phi = s.zeros()
     rels = torch.zeros(max(steps, warm), dtype=torch.float64, device=dev)
+    force = torch.zeros((sph.n, 3), dtype=torch.float64, device=dev)
     sf, first, per = w.extra["subsample"], w.extra["first_cycles"], w.extra["cycles"]
 
     def run(n):
         for t in range(n):
             s.deposit(traj[t], r, q, w.eps, out=f, subsample=sf, mode=pkg.VOLUME)
             s.vcycles(phi, f, first if t == 0 else per, rels[t:t + 1])
+            s.coulomb_force(phi, traj[t], r, q, subsample=sf, mode=pkg.VOLUME, out=force)
 
     run(warm)
     torch.cuda.synchronize()
@@ -158,10 +161,24 @@ def timestep_scene(dev, steps: int):
     secs = ev0.elapsed_time(ev1) / 1e3
     cycles = first + (steps - 1) * per
     rel = rels[:steps].cpu().numpy()
+    # the two sphere kernels alone, same launches
+    ev0.record(stream)
+    for t in range(steps):
+        s.deposit(traj[t], r, q, w.eps, out=f, subsample=sf, mode=pkg.VOLUME)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    dep_ms = ev0.elapsed_time(ev1) / steps
+    ev0.record(stream)
+    for t in range(steps):
+        s.coulomb_force(phi, traj[t], r, q, subsample=sf, mode=pkg.VOLUME, out=force)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    force_ms = ev0.elapsed_time(ev1) / steps
     return {"workload": w.name, "cells": list(w.shape), "spheres": sph.n, "steps": steps, "cycles": cycles,
             "cycle": f"V({w.nu1},{w.nu2})", "levels": s.levels, "coarsest": list(s.level_dims(s.levels - 1)),
             "subsample": sf, "deposition": "volume (q/V per overlapped fraction)", "precision": "fp64",
             "ms_per_step": secs / steps * 1e3, "mlups": w.cells * steps / secs / 1e6,
+            "deposit_ms_per_step": dep_ms, "force_ms_per_step": force_ms,
             "cell_cycles_per_s": w.cells * cycles / secs,
             "rel_res_step0": float(rel[0]), "rel_res_last": float(rel[-1]),
             "rel_res_max_later_steps": float(rel[1:].max()) if steps > 1 else None,

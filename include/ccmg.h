@@ -162,6 +162,27 @@ int ccmg_deposit_charges_sub(ccmg_solver* s, int n, const double* d_centers, con
 int ccmg_charge_gradient(ccmg_solver* s, int n, const double* d_centers, const double* d_radii, double eps,
                          int subsample, int mode, const double* d_lambda, double* d_dq);
 
+/* Gradient of the potential (Sec. 2.4, "Coulomb force": second-order finite
+ * differences, the isotropic D3Q19 lattice stencil where possible): on cells
+ * whose 18 D3Q19 neighbours all lie in the domain,
+ *     grad phi = (1/w_1) sum_q w_q phi(x + h c_q) c_q / h,
+ * w_1 = 1/3, w = 1/18 along the axes and 1/36 along the face diagonals;
+ * on the boundary layer the D3Q7 central differences, with the value beyond
+ * a face taken from the solver's boundary treatment (Sec. 2.4: Dirichlet
+ * 2 g - phi, Neumann phi + h g_n, per-cell face values when set).
+ * d_grad: 3 fields [3][nz][ny][nx] (x, y, z components), overwritten. */
+int ccmg_gradient(ccmg_solver* s, const double* d_phi, double* d_grad);
+
+/* Electrostatic force on each sphere (Sec. 2.4, Eq. ElectrostatForce):
+ *     F_s = -h^3 sum_b grad phi(x_b) rho_s(x_b),
+ * with the gradient of ccmg_gradient and rho_s the sphere's own charge
+ * density of the sub-sampled deposition with the given subsample and mode
+ * (ccmg_deposit_charges_sub; rho, not rho / eps).  d_force (double[3n],
+ * device): F_s in d_force[3s..3s+2], 0 for a sphere covering no sub-cell
+ * centre.  Enqueued without waiting. */
+int ccmg_coulomb_force(ccmg_solver* s, const double* d_phi, int n, const double* d_centers,
+                       const double* d_radii, const double* d_q, int subsample, int mode, double* d_force);
+
 /* Per-cell boundary values on one face (Sec. 2.4, "Boundary conditions"; the
  * validation of Sec. 6.3 sets them to the analytic potential): d_values holds
  * one value per boundary cell of the face, x faces [nz][ny], y faces [nz][nx],

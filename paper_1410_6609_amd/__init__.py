@@ -106,6 +106,8 @@ _SIGS = {
     "ccmg_charge_gradient": ([_VP, ctypes.c_int, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.c_int, _VP, _VP],
                              ctypes.c_int),
     "ccmg_set_face_values": ([_VP, ctypes.c_int, _VP], ctypes.c_int),
+    "ccmg_gradient": ([_VP, _VP, _VP], ctypes.c_int),
+    "ccmg_coulomb_force": ([_VP, _VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_vcycle": ([_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ccmg_vcycles": ([_VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_solve": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
@@ -260,6 +262,30 @@ class Solver:
         self._check(lib().ccmg_charge_gradient(self._h, r.shape[0], _ptr(c), _ptr(r), float(eps), int(subsample),
                                                int(mode), _ptr(lam), _ptr(dq)))
         return dq
+
+    def gradient(self, phi: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """grad phi as a (3, nz, ny, nx) tensor (D3Q19 inside, D3Q7 with boundary ghosts)."""
+        phi = self._field(phi, "phi")
+        nx, ny, nz = self.shape
+        g = torch.empty((3, nz, ny, nx), dtype=torch.float64, device=self.device) if out is None else out
+        if tuple(g.shape) != (3, nz, ny, nx) or g.dtype != torch.float64 or not g.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of shape (3, nz, ny, nx)")
+        self._bind_stream()
+        self._check(lib().ccmg_gradient(self._h, _ptr(phi), _ptr(g)))
+        return g
+
+    def coulomb_force(self, phi: torch.Tensor, centers, radii, q, subsample: int = 1, mode: int = SPREAD,
+                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Electrostatic force per sphere, (n, 3)."""
+        phi = self._field(phi, "phi")
+        c, r = self._spheres(centers, radii)
+        q = q.to(self.device, torch.float64).contiguous().reshape(-1)
+        n = r.shape[0]
+        F = torch.zeros((n, 3), dtype=torch.float64, device=self.device) if out is None else out
+        self._bind_stream()
+        self._check(lib().ccmg_coulomb_force(self._h, _ptr(phi), n, _ptr(c), _ptr(r), _ptr(q), int(subsample),
+                                             int(mode), _ptr(F)))
+        return F
 
     def set_face_values(self, face: int, values: Optional[torch.Tensor]) -> None:
         """Per-cell boundary values of one face (None: back to the constant):

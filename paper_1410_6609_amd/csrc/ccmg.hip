@@ -804,6 +804,34 @@ struct DepositSub {
 };
 
 template <int SF>
+void launch_coulomb(ccmg_solver* s, const double* phi, GradBc B, int n, const double* c, const double* r,
+                    const double* q, int mode, double* force)
+{
+    hipLaunchKernelGGL((k_coulomb<SF>), dim3(n), dim3(kSphereThreads), 0, s->stream, phi, B, c, r, q, mode, force);
+}
+
+template <int SF>
+struct Coulomb {
+    template <typename... A>
+    static void run(A... a) { launch_coulomb<SF>(a...); }
+};
+
+GradBc grad_bc(const ccmg_solver* s)
+{
+    GradBc B{};
+    B.nx = s->nx;
+    B.ny = s->ny;
+    B.nz = s->nz;
+    B.h = s->h;
+    for (int fc = 0; fc < 6; ++fc) {
+        B.dirichlet[fc] = s->bc[fc].kind == CCMG_DIRICHLET;
+        B.value[fc] = s->bc[fc].value;
+        B.face[fc] = s->face_on[fc] ? s->face_vals[fc] : nullptr;
+    }
+    return B;
+}
+
+template <int SF>
 struct DqSub {
     template <typename... A>
     static void run(A... a) { launch_dq_sub<SF>(a...); }
@@ -1012,6 +1040,34 @@ int ccmg_charge_gradient(ccmg_solver* s, int n, const double* d_centers, const d
     NEED_DEV(s, d_lambda, "d_lambda");
     NEED_DEV(s, d_dq, "d_dq");
     by_subsample<DqSub>(subsample, s, n, d_centers, d_radii, eps, mode, d_lambda, d_dq);
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+int ccmg_gradient(ccmg_solver* s, const double* d_phi, double* d_grad)
+{
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    NEED_DEV(s, d_phi, "d_phi");
+    NEED_DEV(s, d_grad, "d_grad");
+    hipLaunchKernelGGL(k_gradient, dim3(grid1d(s->lv[0].n)), dim3(256), 0, s->stream, d_phi, grad_bc(s), d_grad);
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+int ccmg_coulomb_force(ccmg_solver* s, const double* d_phi, int n, const double* d_centers, const double* d_radii,
+                       const double* d_q, int subsample, int mode, double* d_force)
+{
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    if ((rc = check_spheres(s, n, d_centers, d_radii, subsample, mode))) return rc;
+    if (n == 0) return CCMG_OK;
+    NEED_DEV(s, d_phi, "d_phi");
+    NEED_DEV(s, d_q, "d_q");
+    NEED_DEV(s, d_force, "d_force");
+    by_subsample<Coulomb>(subsample, s, d_phi, grad_bc(s), n, d_centers, d_radii, d_q, mode, d_force);
     LAUNCHCHK(s);
     return CCMG_OK;
 }

@@ -1371,4 +1371,131 @@ __global__ __launch_bounds__(kSphereThreads) void k_dq_sub(const double* centers
     if (threadIdx.x == 0) dq[s] = (mode == 0 && W == 0.0) ? 0.0 : sum / sphere_norm(mode, eps, W, R, h);
 }
 
+// ---------------------------------------------------------------------------
+// Potential gradient and electrostatic force (Sec. 2.4, "Coulomb force")
+// ---------------------------------------------------------------------------
+struct GradBc {
+    int nx, ny, nz;
+    double h;
+    int dirichlet[6];
+    double value[6];
+    const double* face[6];   // per-cell boundary values, or null
+};
+
+// phi at (i,j,k), or the ghost value one layer outside across one face:
+// Dirichlet 2 g - phi_b, Neumann phi_b + h g_n (g_n the outward derivative)
+__device__ __forceinline__ double phi_or_ghost(const double* phi, const GradBc& B, int i, int j, int k)
+{
+#pragma clang fp contract(off)
+    int fc = -1, ii = i, jj = j, kk = k;
+    if (i < 0) { fc = 0; ii = 0; }
+    else if (i >= B.nx) { fc = 1; ii = B.nx - 1; }
+    else if (j < 0) { fc = 2; jj = 0; }
+    else if (j >= B.ny) { fc = 3; jj = B.ny - 1; }
+    else if (k < 0) { fc = 4; kk = 0; }
+    else if (k >= B.nz) { fc = 5; kk = B.nz - 1; }
+    const double in = phi[((size_t)kk * B.ny + jj) * B.nx + ii];
+    if (fc < 0) return in;
+    double g = B.value[fc];
+    if (B.face[fc] != nullptr) {
+        const size_t at = fc < 2 ? (size_t)kk * B.ny + jj : fc < 4 ? (size_t)kk * B.nx + ii : (size_t)jj * B.nx + ii;
+        g = B.face[fc][at];
+    }
+    return B.dirichlet[fc] ? 2.0 * g - in : in + B.h * g;
+}
+
+// D3Q19 lattice gradient 3 sum_q w_q phi(x + h c_q) c_q / h (w = 1/18 along
+// the axes, 1/36 along the face diagonals) where all 18 neighbours exist,
+// D3Q7 central differences with boundary ghosts on the boundary layer
+__device__ __forceinline__ void grad_at(const double* phi, const GradBc& B, int i, int j, int k, double& gx,
+                                        double& gy, double& gz)
+{
+#pragma clang fp contract(off)
+    const size_t sy = (size_t)B.nx, sz = (size_t)B.nx * B.ny;
+    if (i > 0 && i < B.nx - 1 && j > 0 && j < B.ny - 1 && k > 0 && k < B.nz - 1) {
+        const double* p = phi + (k * sz + j * sy + i);
+        const double ax = p[1] - p[-1];
+        const double ay = p[sy] - p[-(ptrdiff_t)sy];
+        const double az = p[sz] - p[-(ptrdiff_t)sz];
+        const double xya = p[1 + sy] - p[-1 - (ptrdiff_t)sy];   // (1,1,0) - (-1,-1,0)
+        const double xyb = p[1 - (ptrdiff_t)sy] - p[-1 + (ptrdiff_t)sy];   // (1,-1,0) - (-1,1,0)
+        const double xza = p[1 + sz] - p[-1 - (ptrdiff_t)sz];
+        const double xzb = p[1 - (ptrdiff_t)sz] - p[-1 + (ptrdiff_t)sz];
+        const double yza = p[sy + sz] - p[-(ptrdiff_t)sy - (ptrdiff_t)sz];
+        const double yzb = p[sy - (ptrdiff_t)sz] - p[-(ptrdiff_t)sy + (ptrdiff_t)sz];
+        const double s = 3.0 / B.h;
+        gx = s * (ax * (1.0 / 18.0) + ((xya + xyb) + (xza + xzb)) * (1.0 / 36.0));
+        gy = s * (ay * (1.0 / 18.0) + ((xya - xyb) + (yza + yzb)) * (1.0 / 36.0));
+        gz = s * (az * (1.0 / 18.0) + ((xza - xzb) + (yza - yzb)) * (1.0 / 36.0));
+        return;
+    }
+    const double d = 2.0 * B.h;
+    gx = (phi_or_ghost(phi, B, i + 1, j, k) - phi_or_ghost(phi, B, i - 1, j, k)) / d;
+    gy = (phi_or_ghost(phi, B, i, j + 1, k) - phi_or_ghost(phi, B, i, j - 1, k)) / d;
+    gz = (phi_or_ghost(phi, B, i, j, k + 1) - phi_or_ghost(phi, B, i, j, k - 1)) / d;
+}
+
+__global__ void k_gradient(const double* phi, GradBc B, double* grad)
+{
+    const size_t n = (size_t)B.nx * B.ny * B.nz;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % B.nx), j = (int)((c / B.nx) % B.ny), k = (int)(c / ((size_t)B.nx * B.ny));
+        double gx, gy, gz;
+        grad_at(phi, B, i, j, k, gx, gy, gz);
+        grad[c] = gx;
+        grad[n + c] = gy;
+        grad[2 * n + c] = gz;
+    }
+}
+
+// F_s = -h^3 sum_b grad(phi)(x_b) rho_s(x_b), rho_s = q_s w_b / norm_s (the
+// sphere's own density of the sub-sampled deposition): one workgroup per
+// sphere, one pass over its box
+template <int SF>
+__global__ __launch_bounds__(kSphereThreads) void k_coulomb(const double* phi, GradBc B, const double* centers,
+                                                           const double* radii, const double* q, int mode,
+                                                           double* force)
+{
+#pragma clang fp contract(off)
+    const int s = blockIdx.x;
+    const double cx = centers[3 * s], cy = centers[3 * s + 1], cz = centers[3 * s + 2], R = radii[s];
+    const double R2 = R * R, h = B.h;
+    Box X;
+    ball_box(cx, R, h, B.nx, X.i0, X.i1);
+    ball_box(cy, R, h, B.ny, X.j0, X.j1);
+    ball_box(cz, R, h, B.nz, X.k0, X.k1);
+    const int bx = X.i1 - X.i0 + 1, by = X.j1 - X.j0 + 1, bz = X.k1 - X.k0 + 1;
+    const long long nbox = (bx > 0 && by > 0 && bz > 0) ? (long long)bx * by * bz : 0;
+    double cnt = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+    for (long long c = threadIdx.x; c < nbox; c += kSphereThreads) {
+        const int i = X.i0 + (int)(c % bx), j = X.j0 + (int)((c / bx) % by), k = X.k0 + (int)(c / ((long long)bx * by));
+        const int m = sub_cells_in_ball<SF>(i, j, k, h, cx, cy, cz, R2);
+        if (m > 0) {
+            double gx, gy, gz;
+            grad_at(phi, B, i, j, k, gx, gy, gz);
+            const double w = (double)m / (double)(SF * SF * SF);
+            cnt += (double)m;
+            ax += gx * w;
+            ay += gy * w;
+            az += gz * w;
+        }
+    }
+    const double W = block_sum_d<kSphereThreads>(cnt) / (double)(SF * SF * SF);
+    ax = block_sum_d<kSphereThreads>(ax);
+    ay = block_sum_d<kSphereThreads>(ay);
+    az = block_sum_d<kSphereThreads>(az);
+    if (threadIdx.x == 0) {
+        double* F = force + 3 * (size_t)s;
+        if (W == 0.0) {
+            F[0] = F[1] = F[2] = 0.0;
+        } else {
+            const double norm = sphere_norm(mode, 1.0, W, R, h);
+            const double h3 = h * h * h;
+            F[0] = -h3 * ax * q[s] / norm;
+            F[1] = -h3 * ay * q[s] / norm;
+            F[2] = -h3 * az * q[s] / norm;
+        }
+    }
+}
+
 }  // namespace ccmg
