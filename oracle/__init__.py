@@ -69,6 +69,12 @@ def lib() -> ctypes.CDLL:
             "or_gradient": ([I, I, I, D, ip, dp, ctypes.POINTER(ctypes.c_void_p), dp, dp], None),
             "or_coulomb": ([I, I, I, D, ip, dp, ctypes.POINTER(ctypes.c_void_p), dp, I, dp, dp, dp, I, I, dp],
                            None),
+            "or_vc_faces": ([I, I, I, dp, dp, dp, dp], None),
+            "or_vc_coarsen": ([I, I, I, dp, dp, dp, dp, dp, dp], None),
+            "or_vc_apply": ([I, I, I, D, I, ip, dp, dp, dp, dp, dp], None),
+            "or_vc_rbgs_sweep": ([I, I, I, D, I, ip, dp, dp, dp, dp, dp, I], None),
+            "or_vc_fold": ([I, I, I, D, ip, dp, ctypes.POINTER(ctypes.c_void_p), dp, dp, dp, dp, dp], None),
+            "or_vc_solve": ([I, I, I, D, ip, I, I, I, D, D, I, dp, dp, dp, D, I, dp, ip], I),
             "or_solve": ([I, I, I, D, ip, I, I, I, D, D, I, dp, dp, D, I, dp, ip], I),
             "or_solve_ir": ([I, I, I, D, ip, I, I, I, D, D, I, I, dp, dp, D, I, dp, ip], I),
         }
@@ -313,3 +319,70 @@ def solve_problem(f, h, kinds, values, levels, **kw):
 def adjoint(g, h, kinds, levels, **kw):
     """lambda = A^{-1} g (A symmetric; homogeneous boundary values)."""
     return solve(_f64(g), h, kinds, levels, **kw)
+
+
+# ---- variable permittivity ----------------------------------------------------
+def vc_faces(eps):
+    """Normalised face coefficients (x [nz][ny][nx+1], y [nz][ny+1][nx], z [nz+1][ny][nx])
+    from a cell permittivity [nz][ny][nx]: harmonic means, boundary faces the cell's value."""
+    eps = _f64(eps)
+    nx, ny, nz = _shape(eps)
+    kx, ky, kz = np.empty((nz, ny, nx + 1)), np.empty((nz, ny + 1, nx)), np.empty((nz + 1, ny, nx))
+    lib().or_vc_faces(nx, ny, nz, _dp(eps), _dp(kx), _dp(ky), _dp(kz))
+    return kx, ky, kz
+
+
+def vc_coarsen(k):
+    kx, ky, kz = (_f64(a) for a in k)
+    nz, ny, nx1 = kx.shape
+    nx = nx1 - 1
+    c = (np.empty((nz // 2, ny // 2, nx // 2 + 1)), np.empty((nz // 2, ny // 2 + 1, nx // 2)),
+         np.empty((nz // 2 + 1, ny // 2, nx // 2)))
+    lib().or_vc_coarsen(nx, ny, nz, _dp(kx), _dp(ky), _dp(kz), _dp(c[0]), _dp(c[1]), _dp(c[2]))
+    return c
+
+
+def vc_apply(phi, h, kinds, k, level=0):
+    phi = _f64(phi)
+    nx, ny, nz = _shape(phi)
+    kx, ky, kz = (_f64(a) for a in k)
+    out = np.empty_like(phi)
+    lib().or_vc_apply(nx, ny, nz, h, level, _kinds(kinds), _dp(kx), _dp(ky), _dp(kz), _dp(phi), _dp(out))
+    return out
+
+
+def vc_rbgs_sweep(phi, b, h, kinds, k, level=0, sweeps=1):
+    phi = _f64(phi).copy()
+    b = _f64(b)
+    nx, ny, nz = _shape(phi)
+    kx, ky, kz = (_f64(a) for a in k)
+    lib().or_vc_rbgs_sweep(nx, ny, nz, h, level, _kinds(kinds), _dp(kx), _dp(ky), _dp(kz), _dp(phi), _dp(b), sweeps)
+    return phi
+
+
+def vc_fold(f, h, kinds, values, k, faces=None):
+    f = _f64(f)
+    nx, ny, nz = _shape(f)
+    kx, ky, kz = (_f64(a) for a in k)
+    keep, ptrs = _faces((nx, ny, nz), faces)
+    vals = (ctypes.c_double * 6)(*[float(v) for v in values])
+    b = np.empty_like(f)
+    lib().or_vc_fold(nx, ny, nz, h, _kinds(kinds), vals, ptrs, _dp(kx), _dp(ky), _dp(kz), _dp(f), _dp(b))
+    return b
+
+
+def vc_solve(b, h, kinds, levels, eps, nu1=2, nu2=2, omega=2.0, rtol=1e-10, max_cycles=100, phi0=None,
+             cg_rtol=1e-13, cg_maxit=None):
+    """FP64 multigrid for -div(eps grad phi) on the folded RHS b. Returns (phi, history, status)."""
+    b = _f64(b)
+    eps = _f64(eps)
+    phi = np.zeros_like(b) if phi0 is None else _f64(phi0).copy()
+    nx, ny, nz = _shape(b)
+    hist = np.zeros(max_cycles + 1)
+    cyc = ctypes.c_int(0)
+    cg_maxit = default_cg_maxit((nx, ny, nz), levels) if cg_maxit is None else cg_maxit
+    st = lib().or_vc_solve(nx, ny, nz, h, _kinds(kinds), levels, nu1, nu2, omega, cg_rtol, cg_maxit, _dp(eps),
+                           _dp(b), _dp(phi), rtol, max_cycles, _dp(hist), ctypes.byref(cyc))
+    if st == E_ARG:
+        raise ValueError("oracle: invalid hierarchy")
+    return phi, hist[: cyc.value + 1].copy(), st

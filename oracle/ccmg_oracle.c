@@ -792,3 +792,313 @@ int or_solve_ir(int nx, int ny, int nz, double h, const int* kinds, int levels, 
     hier_free(&H);
     return status;
 }
+
+
+/* ==================== variable permittivity (extension) =====================
+ * -div(eps grad phi) = rho with a cell-wise permittivity (the solver is meant
+ * to be extensible to discontinuous dielectricity by Galerkin coarsening,
+ * Sec. 3; stored per-unknown stencils, Sec. 5.3).  Finite volumes: the flux
+ * across the face between cells a and b is eps_f (phi_b - phi_a) / h with the
+ * harmonic mean eps_f = 2 eps_a eps_b / (eps_a + eps_b); a boundary face takes
+ * the permittivity of its cell.  Level l's operator is s_l times a 7-point
+ * stencil with normalised face coefficients k (s_l = 1/(2^l h^2), k = eps_f on
+ * the finest level):
+ *     (A_l phi)_c = s_l (d_c phi_c - sum over in-domain faces k_f phi_n),
+ *     d_c = sum over in-domain faces k_f + sum over Dirichlet faces 2 k_f
+ * (Neumann faces add nothing).  Galerkin coarsening A_{l+1} = R A_l P with the
+ * cell-centred transfers of Sec. 3 (P copies a coarse value to its 8 children,
+ * R = P^T / 8) keeps this form, with every coarse face coefficient the mean of
+ * the 4 fine face coefficients on that face (derivation: P^T (e_i - e_j)
+ * vanishes for siblings and is e_I - e_J otherwise, so the coarse coupling is
+ * (sum of 4 fine couplings) / 8 = s_{l+1} (sum of 4 k) / 4).  For constant eps
+ * this is eps times the constant-coefficient operator above.
+ * Face arrays: x faces [nz][ny][nx+1], y faces [nz][ny+1][nx], z faces
+ * [nz+1][ny][nx] (face i lies between cells i-1 and i). */
+typedef struct {
+    int nx, ny, nz;
+    double s;
+    int kind[6];
+    double *kx, *ky, *kz;
+} vc_level;
+
+#define VKX(L, i, j, k) ((L)->kx[((size_t)(k) * (L)->ny + (size_t)(j)) * (size_t)((L)->nx + 1) + (size_t)(i)])
+#define VKY(L, i, j, k) ((L)->ky[((size_t)(k) * (size_t)((L)->ny + 1) + (size_t)(j)) * (size_t)(L)->nx + (size_t)(i)])
+#define VKZ(L, i, j, k) ((L)->kz[((size_t)(k) * (L)->ny + (size_t)(j)) * (size_t)(L)->nx + (size_t)(i)])
+
+static size_t vc_nkx(int nx, int ny, int nz) { return (size_t)(nx + 1) * ny * nz; }
+static size_t vc_nky(int nx, int ny, int nz) { return (size_t)nx * (ny + 1) * nz; }
+static size_t vc_nkz(int nx, int ny, int nz) { return (size_t)nx * ny * (nz + 1); }
+
+static double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
+
+static void vc_faces_from_eps(vc_level* L, const double* eps)
+{
+    const int nx = L->nx, ny = L->ny, nz = L->nz;
+#define EPS(i, j, k) eps[((size_t)(k) * ny + (j)) * nx + (i)]
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i <= nx; ++i)
+                VKX(L, i, j, k) = i == 0 ? EPS(0, j, k) : i == nx ? EPS(nx - 1, j, k)
+                                                             : harmonic(EPS(i - 1, j, k), EPS(i, j, k));
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                VKY(L, i, j, k) = j == 0 ? EPS(i, 0, k) : j == ny ? EPS(i, ny - 1, k)
+                                                             : harmonic(EPS(i, j - 1, k), EPS(i, j, k));
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                VKZ(L, i, j, k) = k == 0 ? EPS(i, j, 0) : k == nz ? EPS(i, j, nz - 1)
+                                                             : harmonic(EPS(i, j, k - 1), EPS(i, j, k));
+#undef EPS
+}
+
+/* coarse face coefficient = mean of the 4 fine face coefficients on that face */
+static void vc_coarsen(const vc_level* F, vc_level* C)
+{
+    for (int K = 0; K < C->nz; ++K)
+        for (int J = 0; J < C->ny; ++J)
+            for (int I = 0; I <= C->nx; ++I)
+                VKX(C, I, J, K) = (VKX(F, 2 * I, 2 * J, 2 * K) + VKX(F, 2 * I, 2 * J + 1, 2 * K) +
+                                   VKX(F, 2 * I, 2 * J, 2 * K + 1) + VKX(F, 2 * I, 2 * J + 1, 2 * K + 1)) / 4.0;
+    for (int K = 0; K < C->nz; ++K)
+        for (int J = 0; J <= C->ny; ++J)
+            for (int I = 0; I < C->nx; ++I)
+                VKY(C, I, J, K) = (VKY(F, 2 * I, 2 * J, 2 * K) + VKY(F, 2 * I + 1, 2 * J, 2 * K) +
+                                   VKY(F, 2 * I, 2 * J, 2 * K + 1) + VKY(F, 2 * I + 1, 2 * J, 2 * K + 1)) / 4.0;
+    for (int K = 0; K <= C->nz; ++K)
+        for (int J = 0; J < C->ny; ++J)
+            for (int I = 0; I < C->nx; ++I)
+                VKZ(C, I, J, K) = (VKZ(F, 2 * I, 2 * J, 2 * K) + VKZ(F, 2 * I + 1, 2 * J, 2 * K) +
+                                   VKZ(F, 2 * I, 2 * J + 1, 2 * K) + VKZ(F, 2 * I + 1, 2 * J + 1, 2 * K)) / 4.0;
+}
+
+static double vc_diag(const vc_level* L, int i, int j, int k)
+{
+    double d = 0.0;
+    d += i > 0 ? VKX(L, i, j, k) : (L->kind[0] == OR_DIRICHLET ? 2.0 * VKX(L, 0, j, k) : 0.0);
+    d += i < L->nx - 1 ? VKX(L, i + 1, j, k) : (L->kind[1] == OR_DIRICHLET ? 2.0 * VKX(L, L->nx, j, k) : 0.0);
+    d += j > 0 ? VKY(L, i, j, k) : (L->kind[2] == OR_DIRICHLET ? 2.0 * VKY(L, i, 0, k) : 0.0);
+    d += j < L->ny - 1 ? VKY(L, i, j + 1, k) : (L->kind[3] == OR_DIRICHLET ? 2.0 * VKY(L, i, L->ny, k) : 0.0);
+    d += k > 0 ? VKZ(L, i, j, k) : (L->kind[4] == OR_DIRICHLET ? 2.0 * VKZ(L, i, j, 0) : 0.0);
+    d += k < L->nz - 1 ? VKZ(L, i, j, k + 1) : (L->kind[5] == OR_DIRICHLET ? 2.0 * VKZ(L, i, j, L->nz) : 0.0);
+    return d;
+}
+
+/* sum over in-domain faces of k_f phi_n, order x-, x+, y-, y+, z-, z+ */
+static double vc_nbsum(const vc_level* L, const double* phi, int i, int j, int k)
+{
+    const size_t nx = L->nx, ny = L->ny;
+    const size_t c = ((size_t)k * ny + j) * nx + i;
+    double sum = 0.0;
+    if (i > 0)         sum += VKX(L, i, j, k) * phi[c - 1];
+    if (i < L->nx - 1) sum += VKX(L, i + 1, j, k) * phi[c + 1];
+    if (j > 0)         sum += VKY(L, i, j, k) * phi[c - nx];
+    if (j < L->ny - 1) sum += VKY(L, i, j + 1, k) * phi[c + nx];
+    if (k > 0)         sum += VKZ(L, i, j, k) * phi[c - nx * ny];
+    if (k < L->nz - 1) sum += VKZ(L, i, j, k + 1) * phi[c + nx * ny];
+    return sum;
+}
+
+static size_t vc_cells(const vc_level* L) { return (size_t)L->nx * L->ny * L->nz; }
+
+static void vc_apply(const vc_level* L, const double* phi, double* out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k < L->nz; ++k)
+        for (int j = 0; j < L->ny; ++j)
+            for (int i = 0; i < L->nx; ++i) {
+                const size_t c = ((size_t)k * L->ny + j) * L->nx + i;
+                out[c] = L->s * (vc_diag(L, i, j, k) * phi[c] - vc_nbsum(L, phi, i, j, k));
+            }
+}
+
+static void vc_residual(const vc_level* L, const double* phi, const double* b, double* r)
+{
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k < L->nz; ++k)
+        for (int j = 0; j < L->ny; ++j)
+            for (int i = 0; i < L->nx; ++i) {
+                const size_t c = ((size_t)k * L->ny + j) * L->nx + i;
+                r[c] = b[c] - L->s * (vc_diag(L, i, j, k) * phi[c] - vc_nbsum(L, phi, i, j, k));
+            }
+}
+
+/* red-black Gauss-Seidel, red ((i+j+k) even) first: phi_c <- (b_c/s + sum k phi_n) / d_c */
+static void vc_rbgs_sweep(const vc_level* L, double* phi, const double* b)
+{
+    for (int colour = 0; colour < 2; ++colour) {
+        #pragma omp parallel for schedule(static)
+        for (int k = 0; k < L->nz; ++k)
+            for (int j = 0; j < L->ny; ++j)
+                for (int i = 0; i < L->nx; ++i) {
+                    if (((i + j + k) & 1) != colour) continue;
+                    const size_t c = ((size_t)k * L->ny + j) * L->nx + i;
+                    phi[c] = (b[c] / L->s + vc_nbsum(L, phi, i, j, k)) / vc_diag(L, i, j, k);
+                }
+    }
+}
+
+static int vc_cg(const vc_level* L, const double* b, double* x, double rtol, int maxit)
+{
+    const size_t n = vc_cells(L);
+    double* r = (double*)malloc(n * sizeof(double));
+    double* p = (double*)malloc(n * sizeof(double));
+    double* q = (double*)malloc(n * sizeof(double));
+    for (size_t c = 0; c < n; ++c) { x[c] = 0.0; r[c] = b[c]; p[c] = b[c]; }
+    const double bnorm = norm2_d(n, b);
+    double rr = dot_d(n, r, r);
+    int it = 0;
+    if (bnorm > 0.0) {
+        while (it < maxit) {
+            vc_apply(L, p, q);
+            const double alpha = rr / dot_d(n, p, q);
+            for (size_t c = 0; c < n; ++c) x[c] += alpha * p[c];
+            for (size_t c = 0; c < n; ++c) r[c] -= alpha * q[c];
+            const double rr_new = dot_d(n, r, r);
+            ++it;
+            if (sqrt(rr_new) <= rtol * bnorm) break;
+            const double beta = rr_new / rr;
+            for (size_t c = 0; c < n; ++c) p[c] = r[c] + beta * p[c];
+            rr = rr_new;
+        }
+    }
+    free(r); free(p); free(q);
+    return it;
+}
+
+static vc_level vc_make(int nx, int ny, int nz, double h, int level, const int* kinds, double* kx, double* ky,
+                        double* kz)
+{
+    vc_level L;
+    L.nx = nx; L.ny = ny; L.nz = nz;
+    L.s = 1.0 / (ldexp(1.0, level) * h * h);
+    for (int f = 0; f < 6; ++f) L.kind[f] = kinds[f];
+    L.kx = kx; L.ky = ky; L.kz = kz;
+    return L;
+}
+
+void or_vc_faces(int nx, int ny, int nz, const double* eps, double* kx, double* ky, double* kz)
+{
+    const int kinds[6] = {0, 0, 0, 0, 0, 0};
+    vc_level L = vc_make(nx, ny, nz, 1.0, 0, kinds, kx, ky, kz);
+    vc_faces_from_eps(&L, eps);
+}
+
+/* coarse face arrays of the (nx/2, ny/2, nz/2) level from the fine ones */
+void or_vc_coarsen(int nx, int ny, int nz, const double* kx, const double* ky, const double* kz, double* ckx,
+                   double* cky, double* ckz)
+{
+    const int kinds[6] = {0, 0, 0, 0, 0, 0};
+    vc_level F = vc_make(nx, ny, nz, 1.0, 0, kinds, (double*)kx, (double*)ky, (double*)kz);
+    vc_level C = vc_make(nx / 2, ny / 2, nz / 2, 1.0, 1, kinds, ckx, cky, ckz);
+    vc_coarsen(&F, &C);
+}
+
+void or_vc_apply(int nx, int ny, int nz, double h, int level, const int* kinds, const double* kx, const double* ky,
+                 const double* kz, const double* phi, double* out)
+{
+    vc_level L = vc_make(nx, ny, nz, h, level, kinds, (double*)kx, (double*)ky, (double*)kz);
+    vc_apply(&L, phi, out);
+}
+
+void or_vc_rbgs_sweep(int nx, int ny, int nz, double h, int level, const int* kinds, const double* kx,
+                      const double* ky, const double* kz, double* phi, const double* b, int sweeps)
+{
+    vc_level L = vc_make(nx, ny, nz, h, level, kinds, (double*)kx, (double*)ky, (double*)kz);
+    for (int s = 0; s < sweeps; ++s) vc_rbgs_sweep(&L, phi, b);
+}
+
+/* b = f + boundary terms with the boundary face coefficients: Dirichlet
+ * 2 k_f g / h^2, Neumann k_f g_n / h (the flux eps dphi/dn = eps g_n), faces in
+ * the order x-, x+, y-, y+, z-, z+; face[fc] (nullable) gives per-cell values
+ * as in or_fold_field. */
+void or_vc_fold(int nx, int ny, int nz, double h, const int* kinds, const double* values, const double* const* face,
+                const double* kx, const double* ky, const double* kz, const double* f, double* b)
+{
+    vc_level L = vc_make(nx, ny, nz, h, 0, kinds, (double*)kx, (double*)ky, (double*)kz);
+    const size_t n = vc_cells(&L);
+    for (size_t c = 0; c < n; ++c) b[c] = f[c];
+    for (int fc = 0; fc < 6; ++fc) {
+        const int ax = fc / 2, hi = fc % 2;
+        const int n0 = ax == 0 ? ny : nx;
+        const int n1 = ax == 2 ? ny : nz;
+        for (int v = 0; v < n1; ++v)
+            for (int u = 0; u < n0; ++u) {
+                const double g = (face && face[fc]) ? face[fc][(size_t)v * n0 + u] : values[fc];
+                int i, j, k;
+                double kf;
+                if (ax == 0)      { i = hi ? nx - 1 : 0; j = u; k = v; kf = VKX(&L, hi ? nx : 0, j, k); }
+                else if (ax == 1) { j = hi ? ny - 1 : 0; i = u; k = v; kf = VKY(&L, i, hi ? ny : 0, k); }
+                else              { k = hi ? nz - 1 : 0; i = u; j = v; kf = VKZ(&L, i, j, hi ? nz : 0); }
+                const double t = kinds[fc] == OR_DIRICHLET ? 2.0 * kf * g / (h * h) : kf * g / h;
+                b[((size_t)k * ny + j) * nx + i] += t;
+            }
+    }
+}
+
+/* V(nu1,nu2)-cycles for the variable-permittivity operator (same cycle as
+ * or_solve: smoothing, residual, averaging restriction, zero coarse guess,
+ * CG on the coarsest level, nearest-neighbour prolongation times omega),
+ * every level's face coefficients by Galerkin coarsening of the finest. */
+int or_vc_solve(int nx, int ny, int nz, double h, const int* kinds, int levels, int nu1, int nu2, double omega,
+                double cg_rtol, int cg_maxit, const double* eps, const double* b, double* phi, double rtol,
+                int max_cycles, double* hist, int* cycles_out)
+{
+    if (levels < 1 || levels > OR_MAXLEVELS) return OR_E_ARG;
+    const int div = 1 << (levels - 1);
+    if (nx % div || ny % div || nz % div) return OR_E_ARG;
+    vc_level L[OR_MAXLEVELS];
+    double *ph[OR_MAXLEVELS], *bb[OR_MAXLEVELS], *rr[OR_MAXLEVELS];
+    for (int l = 0; l < levels; ++l) {
+        const int a = nx >> l, bq = ny >> l, c = nz >> l;
+        L[l] = vc_make(a, bq, c, h, l, kinds, (double*)malloc(vc_nkx(a, bq, c) * sizeof(double)),
+                       (double*)malloc(vc_nky(a, bq, c) * sizeof(double)),
+                       (double*)malloc(vc_nkz(a, bq, c) * sizeof(double)));
+        const size_t n = vc_cells(&L[l]);
+        ph[l] = l == 0 ? phi : (double*)calloc(n, sizeof(double));
+        bb[l] = l == 0 ? (double*)b : (double*)calloc(n, sizeof(double));
+        rr[l] = (double*)calloc(n, sizeof(double));
+        if (l == 0) vc_faces_from_eps(&L[0], eps);
+        else vc_coarsen(&L[l - 1], &L[l]);
+    }
+    const size_t n0 = vc_cells(&L[0]);
+    const double bnorm = norm2_d(n0, b);
+    int k = 0, status = OR_OK;
+    if (bnorm == 0.0) {
+        memset(phi, 0, n0 * sizeof(double));
+        if (hist) hist[0] = 0.0;
+    } else {
+        vc_residual(&L[0], phi, b, rr[0]);
+        double rho = norm2_d(n0, rr[0]) / bnorm;
+        if (hist) hist[0] = rho;
+        while (isfinite(rho) && rho >= rtol && k < max_cycles) {
+            for (int l = 0; l < levels - 1; ++l) {
+                for (int s = 0; s < nu1; ++s) vc_rbgs_sweep(&L[l], ph[l], bb[l]);
+                vc_residual(&L[l], ph[l], bb[l], rr[l]);
+                const or_level dims = make_level(L[l].nx, L[l].ny, L[l].nz, h, l, kinds);
+                restrict_avg_d(&dims, rr[l], bb[l + 1]);
+                memset(ph[l + 1], 0, vc_cells(&L[l + 1]) * sizeof(double));
+            }
+            vc_cg(&L[levels - 1], bb[levels - 1], ph[levels - 1], cg_rtol, cg_maxit);
+            for (int l = levels - 2; l >= 0; --l) {
+                const or_level dims = make_level(L[l].nx, L[l].ny, L[l].nz, h, l, kinds);
+                prolong_add_d(&dims, ph[l + 1], omega, ph[l]);
+                for (int s = 0; s < nu2; ++s) vc_rbgs_sweep(&L[l], ph[l], bb[l]);
+            }
+            ++k;
+            vc_residual(&L[0], phi, b, rr[0]);
+            rho = norm2_d(n0, rr[0]) / bnorm;
+            if (hist) hist[k] = rho;
+        }
+        if (!isfinite(rho)) status = OR_E_NONFINITE;
+        else if (rho >= rtol) status = OR_E_NOCONV;
+    }
+    if (cycles_out) *cycles_out = k;
+    for (int l = 0; l < levels; ++l) {
+        free(L[l].kx); free(L[l].ky); free(L[l].kz);
+        if (l > 0) { free(ph[l]); free(bb[l]); }
+        free(rr[l]);
+    }
+    return status;
+}
