@@ -80,6 +80,8 @@ typedef struct {
     int fuse_sweeps;      /* RB-GS sweeps fused per smoother kernel pass: 1 or 2 (default 2); iterates are identical */
     int bottom_cells;     /* the coarse levels from the first one with at most this many cells down to the
                              coarsest run in one workgroup, in LDS (default 4096, the maximum; 0 = off) */
+    int variable_eps;     /* 1: reserve stored face coefficients for a cell-wise permittivity
+                             (ccmg_set_permittivity; FP64 only); default 0 */
 } ccmg_options;
 
 typedef struct {
@@ -182,6 +184,25 @@ int ccmg_gradient(ccmg_solver* s, const double* d_phi, double* d_grad);
  * centre.  Enqueued without waiting. */
 int ccmg_coulomb_force(ccmg_solver* s, const double* d_phi, int n, const double* d_centers,
                        const double* d_radii, const double* d_q, int subsample, int mode, double* d_force);
+
+/* Cell-wise permittivity (extension for discontinuous dielectricity, which
+ * the paper's solver is designed for by Galerkin coarsening, Sec. 3, with
+ * per-unknown stencils, Sec. 5.3).  Needs a solver created with
+ * opt.variable_eps = 1 (else E_STATE) and its workspace.  d_eps: one positive
+ * value per cell, [nz][ny][nx] (device; read during the call's kernels only).
+ * From then on every solve, cycle, residual and smoothing call of this solver
+ * uses -div(eps grad phi) = f with d_f = rho (not rho / eps):
+ *   - the flux across an interior face is eps_f (phi_b - phi_a) / h with the
+ *     harmonic mean eps_f = 2 eps_a eps_b / (eps_a + eps_b); a boundary face
+ *     takes its cell's eps (Dirichlet 2 eps_f (phi_c - g) / h, Neumann flux
+ *     eps_f g_n);
+ *   - coarse levels by Galerkin coarsening R A P with the cell-centred
+ *     transfers, which keeps a 7-point stencil whose face coefficients are
+ *     the means of the 4 fine face coefficients (times the level scale);
+ *   - the same V(nu1,nu2)-cycle, stopping rule, adjoint and statistics.
+ * d_eps = NULL returns to the constant-coefficient operator (-Lap phi = f).
+ * Enqueued without waiting. */
+int ccmg_set_permittivity(ccmg_solver* s, const double* d_eps);
 
 /* Per-cell boundary values on one face (Sec. 2.4, "Boundary conditions"; the
  * validation of Sec. 6.3 sets them to the analytic potential): d_values holds

@@ -50,7 +50,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("levels", ctypes.c_int),
                 ("omega", ctypes.c_double), ("precision", ctypes.c_int),
                 ("ir_inner_cycles", ctypes.c_int), ("cg_rtol", ctypes.c_double),
-                ("cg_maxit", ctypes.c_int), ("fuse_sweeps", ctypes.c_int), ("bottom_cells", ctypes.c_int)]
+                ("cg_maxit", ctypes.c_int), ("fuse_sweeps", ctypes.c_int), ("bottom_cells", ctypes.c_int),
+                ("variable_eps", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -71,11 +72,12 @@ class Options:
     cg_maxit: int = 0
     fuse_sweeps: int = 2
     bottom_cells: int = 4096
+    variable_eps: int = 0
 
     def _c(self) -> _Options:
         return _Options(self.nu1, self.nu2, self.levels, self.omega, self.precision,
                         self.ir_inner_cycles, self.cg_rtol, self.cg_maxit, self.fuse_sweeps,
-                        self.bottom_cells)
+                        self.bottom_cells, self.variable_eps)
 
 
 @dataclass
@@ -107,6 +109,7 @@ _SIGS = {
                              ctypes.c_int),
     "ccmg_set_face_values": ([_VP, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_gradient": ([_VP, _VP, _VP], ctypes.c_int),
+    "ccmg_set_permittivity": ([_VP, _VP], ctypes.c_int),
     "ccmg_coulomb_force": ([_VP, _VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_vcycle": ([_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ccmg_vcycles": ([_VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
@@ -286,6 +289,16 @@ class Solver:
         self._check(lib().ccmg_coulomb_force(self._h, _ptr(phi), n, _ptr(c), _ptr(r), _ptr(q), int(subsample),
                                              int(mode), _ptr(F)))
         return F
+
+    def set_permittivity(self, eps: Optional[torch.Tensor]) -> None:
+        """Cell-wise permittivity (None: back to the constant operator); needs
+        Options(variable_eps=1).  Afterwards solves take f = rho."""
+        v = None
+        if eps is not None:
+            v = self._field(eps.to(self.device, torch.float64).contiguous(), "eps")
+        self._bind_stream()
+        self._check(lib().ccmg_set_permittivity(self._h, _ptr(v)))
+        self._eps_keep = v   # read by the enqueued kernels
 
     def set_face_values(self, face: int, values: Optional[torch.Tensor]) -> None:
         """Per-cell boundary values of one face (None: back to the constant):

@@ -118,6 +118,11 @@ struct ccmg_solver {
     int max_partials = 0;
     double* face_vals[6] = {};   // per-cell boundary values (workspace)
     bool face_on[6] = {};        // face uses face_vals instead of bc[].value
+    // variable permittivity: stored face coefficients per level (workspace)
+    double* vkx[CCMG_MAX_LEVELS] = {};
+    double* vky[CCMG_MAX_LEVELS] = {};
+    double* vkz[CCMG_MAX_LEVELS] = {};
+    bool vc_on = false;
     // kernel timing (ccmg_profile_*)
     bool prof = false;
     struct ProfRec { int cycle, which; hipEvent_t a, b; };
@@ -525,8 +530,90 @@ int enqueue_ctl_init(ccmg_solver* s, double rtol)
 }
 
 // b-tilde_0 = h^2 (f + boundary terms); homogeneous=true drops the boundary values
+// ---- variable permittivity -----------------------------------------------
+VcLevel vc_level(const ccmg_solver* s, int l)
+{
+    VcLevel V{};
+    V.kx = s->vkx[l];
+    V.ky = s->vky[l];
+    V.kz = s->vkz[l];
+    V.nx = s->lv[l].nx;
+    V.ny = s->lv[l].ny;
+    V.nz = s->lv[l].nz;
+    for (int fc = 0; fc < 6; ++fc) V.dir[fc] = s->bc[fc].kind == CCMG_DIRICHLET;
+    return V;
+}
+
+int vc_grid(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 4096); }
+
+int enqueue_vc_fold(ccmg_solver* s, const double* f, bool homogeneous)
+{
+    VcFold P{};
+    P.f = f;
+    P.bt = s->lv[0].b;
+    P.h = s->h;
+    P.homogeneous = homogeneous;
+    for (int fc = 0; fc < 6; ++fc) {
+        P.value[fc] = s->bc[fc].value;
+        P.face[fc] = s->face_on[fc] ? s->face_vals[fc] : nullptr;
+    }
+    hipLaunchKernelGGL(k_vc_fold, dim3(vc_grid(s->lv[0].n)), dim3(256), 0, s->stream, P, vc_level(s, 0));
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+int enqueue_vc_norm(ccmg_solver* s, const double* phi, int fin, double* r_out, double rscale, int cycle)
+{
+    const int g = std::max(1, std::min(vc_grid(s->lv[0].n), s->max_partials));
+    hipLaunchKernelGGL(k_vc_norm, dim3(g), dim3(kVcNormThreads), 0, s->stream, vc_level(s, 0), phi,
+                       (const double*)s->lv[0].b, r_out, rscale, s->partials, s->ctl, fin, cycle);
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+void enqueue_vc_sweeps(ccmg_solver* s, int l, double* phi, int sweeps)
+{
+    const VcLevel V = vc_level(s, l);
+    const size_t half = ((size_t)(V.nx + 1) / 2) * V.ny * V.nz;
+    for (int k = 0; k < sweeps; ++k)
+        for (int colour = 0; colour < 2; ++colour)
+            hipLaunchKernelGGL(k_vc_sweep, dim3(vc_grid(half)), dim3(256), 0, s->stream, V, phi,
+                               (const double*)s->lv[l].b, colour, (const Ctl*)s->ctl);
+}
+
+// one V(nu1,nu2)-cycle on the variable-permittivity hierarchy; fin_cycle > 0
+// finalises the finest residual norm as that cycle
+int enqueue_vc_cycle(ccmg_solver* s, double* phi0, int fin_cycle)
+{
+    const int L = s->L;
+    auto home = [&](int l) { return l == 0 ? phi0 : s->lv[l].phi; };
+    for (int l = 0; l + 1 < L; ++l) {
+        enqueue_vc_sweeps(s, l, home(l), s->opt.nu1);
+        const size_t nc = s->lv[l + 1].n;
+        hipLaunchKernelGGL(k_vc_restrict, dim3(vc_grid(nc)), dim3(256), 0, s->stream, vc_level(s, l),
+                           (const double*)home(l), (const double*)s->lv[l].b, s->lv[l + 1].b, home(l + 1),
+                           (const Ctl*)s->ctl);
+    }
+    {
+        const VcLevel V = vc_level(s, L - 1);
+        const size_t lds = 4 * sizeof(double) * s->lv[L - 1].n;
+        hipLaunchKernelGGL(k_vc_cg, dim3(1), dim3(kVcCgThreads), lds, s->stream, V, (const double*)s->lv[L - 1].b,
+                           home(L - 1), s->opt.cg_rtol, s->cg_maxit, (const Ctl*)s->ctl);
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        hipLaunchKernelGGL(k_vc_prolong, dim3(vc_grid(s->lv[l].n)), dim3(256), 0, s->stream, home(l),
+                           (const double*)home(l + 1), s->lv[l].nx, s->lv[l].ny, s->lv[l].nz, s->opt.omega,
+                           (const Ctl*)s->ctl);
+        enqueue_vc_sweeps(s, l, home(l), s->opt.nu2);
+    }
+    LAUNCHCHK(s);
+    if (fin_cycle > 0) return enqueue_vc_norm(s, phi0, FIN_CYCLE, nullptr, 0.0, fin_cycle);
+    return CCMG_OK;
+}
+
 int enqueue_fold(ccmg_solver* s, const double* f, bool homogeneous)
 {
+    if (s->vc_on) return enqueue_vc_fold(s, f, homogeneous);
     const LevelBuf& B = s->lv[0];
     FoldParams P{};
     P.f = f;
@@ -550,6 +637,10 @@ int enqueue_fold(ccmg_solver* s, const double* f, bool homogeneous)
 // residual-norm pass on the finest level (FP64) finalised as `fin`
 int enqueue_norm(ccmg_solver* s, const double* phi, int fin, int res, double* r_out, float* r32_out, int cycle)
 {
+    if (s->vc_on) {
+        if (res != RES_NORM) return fail(s, CCMG_E_ARG, "internal: norm kind with variable permittivity");
+        return enqueue_vc_norm(s, phi, fin, r_out, 0.0, cycle);
+    }
     PassParams<double> P = base_params<double>(s, 0);
     P.phi_in = phi;
     P.b = s->lv[0].b;
@@ -660,7 +751,9 @@ int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_
     int inner = 1;
     if (s->opt.precision == CCMG_FP64) {
         const LevelPtrs<double> H = fp64_ptrs(s, phi);
-        rc = run_loop(s, max_cycles, [&](int k) { return enqueue_vcycle<double>(s, H, false, k); }, h);
+        rc = run_loop(s, max_cycles, [&](int k) {
+            return s->vc_on ? enqueue_vc_cycle(s, phi, k) : enqueue_vcycle<double>(s, H, false, k);
+        }, h);
     } else {
         inner = s->opt.ir_inner_cycles;
         const LevelPtrs<float> H = fp32_ptrs(s);
@@ -720,6 +813,15 @@ size_t layout_workspace(ccmg_solver* s, char* base)
     for (int fc = 0; fc < 6; ++fc) {
         double* fv = (double*)take(sizeof(double) * face_cells(s, fc));
         if (base) s->face_vals[fc] = fv;
+    }
+    if (s->opt.variable_eps) {
+        for (int l = 0; l < s->L; ++l) {
+            const size_t a = s->lv[l].nx, b = s->lv[l].ny, c = s->lv[l].nz;
+            double* kx = (double*)take(sizeof(double) * (a + 1) * b * c);
+            double* ky = (double*)take(sizeof(double) * a * (b + 1) * c);
+            double* kz = (double*)take(sizeof(double) * a * b * (c + 1));
+            if (base) { s->vkx[l] = kx; s->vky[l] = ky; s->vkz[l] = kz; }
+        }
     }
     for (int l = 0; l < s->L; ++l) {
         LevelBuf& B = s->lv[l];
@@ -867,6 +969,7 @@ void ccmg_default_options(ccmg_options* o)
     o->cg_maxit = 0;
     o->fuse_sweeps = 2;
     o->bottom_cells = kBottomMaxCells;
+    o->variable_eps = 0;
 }
 
 int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_face bc[6],
@@ -888,6 +991,9 @@ int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_
     if (!std::isfinite(o.omega)) return fail(nullptr, CCMG_E_ARG, "bad omega");
     if (o.bottom_cells < 0 || o.bottom_cells > kBottomMaxCells)
         return fail(nullptr, CCMG_E_ARG, "bottom_cells must be in 0..%d", kBottomMaxCells);
+    if (o.variable_eps != 0 && o.variable_eps != 1) return fail(nullptr, CCMG_E_ARG, "variable_eps must be 0 or 1");
+    if (o.variable_eps && o.precision != CCMG_FP64)
+        return fail(nullptr, CCMG_E_ARG, "variable permittivity is solved in FP64 only");
     bool any_dirichlet = false;
     for (int f = 0; f < 6; ++f) {
         if (bc[f].kind != CCMG_DIRICHLET && bc[f].kind != CCMG_NEUMANN) return fail(nullptr, CCMG_E_ARG, "bad face kind");
@@ -1072,6 +1178,34 @@ int ccmg_coulomb_force(ccmg_solver* s, const double* d_phi, int n, const double*
     return CCMG_OK;
 }
 
+int ccmg_set_permittivity(ccmg_solver* s, const double* d_eps)
+{
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    if (!s->opt.variable_eps) return fail(s, CCMG_E_STATE, "solver created without variable_eps");
+    if (d_eps == nullptr) {
+        s->vc_on = false;
+        return CCMG_OK;
+    }
+    NEED_DEV(s, d_eps, "d_eps");
+    const LevelBuf& B = s->lv[0];
+    const size_t nf = (size_t)(B.nx + 1) * B.ny * B.nz + (size_t)B.nx * (B.ny + 1) * B.nz +
+                      (size_t)B.nx * B.ny * (B.nz + 1);
+    hipLaunchKernelGGL(k_vc_faces, dim3(vc_grid(nf)), dim3(256), 0, s->stream, d_eps, s->vkx[0], s->vky[0], s->vkz[0],
+                       B.nx, B.ny, B.nz);
+    for (int l = 0; l + 1 < s->L; ++l) {
+        const LevelBuf& C = s->lv[l + 1];
+        const size_t nc = (size_t)(C.nx + 1) * C.ny * C.nz + (size_t)C.nx * (C.ny + 1) * C.nz +
+                          (size_t)C.nx * C.ny * (C.nz + 1);
+        hipLaunchKernelGGL(k_vc_coarsen, dim3(vc_grid(nc)), dim3(256), 0, s->stream, vc_level(s, l), s->vkx[l + 1],
+                           s->vky[l + 1], s->vkz[l + 1], C.nx, C.ny, C.nz);
+    }
+    LAUNCHCHK(s);
+    s->vc_on = true;
+    return CCMG_OK;
+}
+
 int ccmg_set_face_values(ccmg_solver* s, int face, const double* d_values)
 {
     if (!s) return CCMG_E_ARG;
@@ -1096,6 +1230,7 @@ namespace {
 int enqueue_cycle(ccmg_solver* s, double* d_phi, bool norm)
 {
     int rc;
+    if (s->vc_on) return enqueue_vc_cycle(s, d_phi, norm ? 1 : 0);
     if (s->opt.precision == CCMG_FP64) return enqueue_vcycle<double>(s, fp64_ptrs(s, d_phi), false, norm ? 1 : 0);
     // FP32 cycles on the scaled residual, FP64 update (the update pass also
     // reduces the next residual norm)
@@ -1226,14 +1361,18 @@ int ccmg_residual(ccmg_solver* s, const double* d_phi, const double* d_f, double
     if (d_r) NEED_DEV(s, d_r, "d_r");
     if ((rc = enqueue_ctl_init(s, -1.0))) return rc;
     if ((rc = enqueue_fold(s, d_f, false))) return rc;
-    PassParams<double> P = base_params<double>(s, 0);
-    P.phi_in = d_phi;
-    P.b = s->lv[0].b;
-    P.fin = FIN_STORE;
-    P.r_out = d_r;
-    P.rscale = 1.0 / (s->h * s->h);
-    if (!dispatch<double>(0, LOAD_PHI, RES_STORE, P, s->stream)) return fail(s, CCMG_E_ARG, "residual pass");
-    LAUNCHCHK(s);
+    if (s->vc_on) {
+        if ((rc = enqueue_vc_norm(s, d_phi, FIN_STORE, d_r, 1.0 / (s->h * s->h), 0))) return rc;
+    } else {
+        PassParams<double> P = base_params<double>(s, 0);
+        P.phi_in = d_phi;
+        P.b = s->lv[0].b;
+        P.fin = FIN_STORE;
+        P.r_out = d_r;
+        P.rscale = 1.0 / (s->h * s->h);
+        if (!dispatch<double>(0, LOAD_PHI, RES_STORE, P, s->stream)) return fail(s, CCMG_E_ARG, "residual pass");
+        LAUNCHCHK(s);
+    }
     if (rel_res_out) {
         CtlHead h;
         if ((rc = read_ctl(s, h, -1))) return rc;
@@ -1253,6 +1392,11 @@ int ccmg_smooth(ccmg_solver* s, double* d_phi, const double* d_f, int sweeps)
     if (sweeps == 0) return CCMG_OK;
     if ((rc = enqueue_ctl_init(s, -1.0))) return rc;
     if ((rc = enqueue_fold(s, d_f, false))) return rc;
+    if (s->vc_on) {
+        enqueue_vc_sweeps(s, 0, d_phi, sweeps);
+        LAUNCHCHK(s);
+        return CCMG_OK;
+    }
     const int fuse = s->opt.fuse_sweeps;
     std::vector<PassSpec> ps;
     for (int left = sweeps; left > 0;) {

@@ -1498,4 +1498,276 @@ __global__ __launch_bounds__(kSphereThreads) void k_coulomb(const double* phi, G
     }
 }
 
+// ---------------------------------------------------------------------------
+// Variable permittivity: -div(eps grad phi) = rho with stored face
+// coefficients (Galerkin coarsening with the cell-centred transfers, Sec. 3;
+// per-unknown stencils, Sec. 5.3).  Level l's operator is s_l times the
+// 7-point stencil with normalised face coefficients k (k = harmonic-mean eps
+// on the finest level, the mean of the 4 fine faces on a coarse face):
+//     d_c phi_c - sum over in-domain faces k_f phi_n,
+//     d_c = sum over in-domain faces k_f + 2 k_f per Dirichlet boundary face.
+// Face arrays: x faces [nz][ny][nx+1], y faces [nz][ny+1][nx], z faces
+// [nz+1][ny][nx] (face i between cells i-1 and i).
+// ---------------------------------------------------------------------------
+struct VcLevel {
+    const double* kx;
+    const double* ky;
+    const double* kz;
+    int nx, ny, nz;
+    int dir[6];   // 1: Dirichlet face
+};
+
+__device__ __forceinline__ size_t vc_ix(const VcLevel& L, int i, int j, int k)
+{
+    return ((size_t)k * L.ny + j) * (size_t)(L.nx + 1) + i;
+}
+__device__ __forceinline__ size_t vc_iy(const VcLevel& L, int i, int j, int k)
+{
+    return ((size_t)k * (L.ny + 1) + j) * (size_t)L.nx + i;
+}
+__device__ __forceinline__ size_t vc_iz(const VcLevel& L, int i, int j, int k)
+{
+    return ((size_t)k * L.ny + j) * (size_t)L.nx + i;
+}
+
+// diagonal and weighted neighbour sum of cell (i,j,k)
+__device__ __forceinline__ void vc_row(const VcLevel& L, const double* phi, int i, int j, int k, double& d,
+                                       double& sum)
+{
+    const size_t sy = (size_t)L.nx, sz = (size_t)L.nx * L.ny;
+    const size_t c = (size_t)k * sz + (size_t)j * sy + i;
+    const double kxm = L.kx[vc_ix(L, i, j, k)], kxp = L.kx[vc_ix(L, i + 1, j, k)];
+    const double kym = L.ky[vc_iy(L, i, j, k)], kyp = L.ky[vc_iy(L, i, j + 1, k)];
+    const double kzm = L.kz[vc_iz(L, i, j, k)], kzp = L.kz[vc_iz(L, i, j, k + 1)];
+    double dd = 0.0, ss = 0.0;
+    if (i > 0) { dd += kxm; ss += kxm * phi[c - 1]; } else if (L.dir[0]) dd += 2.0 * kxm;
+    if (i < L.nx - 1) { dd += kxp; ss += kxp * phi[c + 1]; } else if (L.dir[1]) dd += 2.0 * kxp;
+    if (j > 0) { dd += kym; ss += kym * phi[c - sy]; } else if (L.dir[2]) dd += 2.0 * kym;
+    if (j < L.ny - 1) { dd += kyp; ss += kyp * phi[c + sy]; } else if (L.dir[3]) dd += 2.0 * kyp;
+    if (k > 0) { dd += kzm; ss += kzm * phi[c - sz]; } else if (L.dir[4]) dd += 2.0 * kzm;
+    if (k < L.nz - 1) { dd += kzp; ss += kzp * phi[c + sz]; } else if (L.dir[5]) dd += 2.0 * kzp;
+    d = dd;
+    sum = ss;
+}
+
+__device__ __forceinline__ double harmonic_mean(double a, double b) { return 2.0 * a * b / (a + b); }
+
+// finest-level face coefficients from the cell permittivity: one thread per
+// face of each orientation (boundary faces take their cell's value)
+__global__ void k_vc_faces(const double* eps, double* kx, double* ky, double* kz, int nx, int ny, int nz)
+{
+    const size_t nfx = (size_t)(nx + 1) * ny * nz, nfy = (size_t)nx * (ny + 1) * nz, nfz = (size_t)nx * ny * (nz + 1);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    auto E = [&](int i, int j, int k) { return eps[((size_t)k * ny + j) * nx + i]; };
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nfx + nfy + nfz; t += stride) {
+        if (t < nfx) {
+            const int i = (int)(t % (nx + 1)), j = (int)((t / (nx + 1)) % ny), k = (int)(t / ((size_t)(nx + 1) * ny));
+            kx[t] = i == 0 ? E(0, j, k) : i == nx ? E(nx - 1, j, k) : harmonic_mean(E(i - 1, j, k), E(i, j, k));
+        } else if (t < nfx + nfy) {
+            const size_t u = t - nfx;
+            const int i = (int)(u % nx), j = (int)((u / nx) % (ny + 1)), k = (int)(u / ((size_t)nx * (ny + 1)));
+            ky[u] = j == 0 ? E(i, 0, k) : j == ny ? E(i, ny - 1, k) : harmonic_mean(E(i, j - 1, k), E(i, j, k));
+        } else {
+            const size_t u = t - nfx - nfy;
+            const int i = (int)(u % nx), j = (int)((u / nx) % ny), k = (int)(u / ((size_t)nx * ny));
+            kz[u] = k == 0 ? E(i, j, 0) : k == nz ? E(i, j, nz - 1) : harmonic_mean(E(i, j, k - 1), E(i, j, k));
+        }
+    }
+}
+
+// Galerkin coarsening: every coarse face coefficient is the mean of the 4
+// fine face coefficients on that face (F: fine level, C: coarse level)
+__global__ void k_vc_coarsen(VcLevel F, double* ckx, double* cky, double* ckz, int cnx, int cny, int cnz)
+{
+    const size_t nfx = (size_t)(cnx + 1) * cny * cnz, nfy = (size_t)cnx * (cny + 1) * cnz,
+                 nfz = (size_t)cnx * cny * (cnz + 1);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nfx + nfy + nfz; t += stride) {
+        if (t < nfx) {
+            const int I = (int)(t % (cnx + 1)), J = (int)((t / (cnx + 1)) % cny), K = (int)(t / ((size_t)(cnx + 1) * cny));
+            ckx[t] = (F.kx[vc_ix(F, 2 * I, 2 * J, 2 * K)] + F.kx[vc_ix(F, 2 * I, 2 * J + 1, 2 * K)] +
+                      F.kx[vc_ix(F, 2 * I, 2 * J, 2 * K + 1)] + F.kx[vc_ix(F, 2 * I, 2 * J + 1, 2 * K + 1)]) * 0.25;
+        } else if (t < nfx + nfy) {
+            const size_t u = t - nfx;
+            const int I = (int)(u % cnx), J = (int)((u / cnx) % (cny + 1)), K = (int)(u / ((size_t)cnx * (cny + 1)));
+            cky[u] = (F.ky[vc_iy(F, 2 * I, 2 * J, 2 * K)] + F.ky[vc_iy(F, 2 * I + 1, 2 * J, 2 * K)] +
+                      F.ky[vc_iy(F, 2 * I, 2 * J, 2 * K + 1)] + F.ky[vc_iy(F, 2 * I + 1, 2 * J, 2 * K + 1)]) * 0.25;
+        } else {
+            const size_t u = t - nfx - nfy;
+            const int I = (int)(u % cnx), J = (int)((u / cnx) % cny), K = (int)(u / ((size_t)cnx * cny));
+            ckz[u] = (F.kz[vc_iz(F, 2 * I, 2 * J, 2 * K)] + F.kz[vc_iz(F, 2 * I + 1, 2 * J, 2 * K)] +
+                      F.kz[vc_iz(F, 2 * I, 2 * J + 1, 2 * K)] + F.kz[vc_iz(F, 2 * I + 1, 2 * J + 1, 2 * K)]) * 0.25;
+        }
+    }
+}
+
+// b-tilde = h^2 (f + boundary terms): Dirichlet 2 k_f g / h^2, Neumann k_f g_n / h,
+// per-cell face values when given, faces added in the order x-, x+, y-, y+, z-, z+
+struct VcFold {
+    const double* f;
+    double* bt;
+    double h;
+    double value[6];
+    const double* face[6];
+    int homogeneous;
+};
+
+__device__ __forceinline__ double vc_bterm(const VcFold& P, const VcLevel& L, int fc, size_t at, double kf)
+{
+    if (P.homogeneous) return 0.0;
+    const double g = P.face[fc] != nullptr ? P.face[fc][at] : P.value[fc];
+    return L.dir[fc] ? 2.0 * kf * g / (P.h * P.h) : kf * g / P.h;
+}
+
+__global__ void k_vc_fold(VcFold P, VcLevel L)
+{
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const size_t n = (size_t)nx * ny * nz;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+        double v = P.f[c];
+        if (i == 0) v += vc_bterm(P, L, 0, (size_t)k * ny + j, L.kx[vc_ix(L, 0, j, k)]);
+        if (i == nx - 1) v += vc_bterm(P, L, 1, (size_t)k * ny + j, L.kx[vc_ix(L, nx, j, k)]);
+        if (j == 0) v += vc_bterm(P, L, 2, (size_t)k * nx + i, L.ky[vc_iy(L, i, 0, k)]);
+        if (j == ny - 1) v += vc_bterm(P, L, 3, (size_t)k * nx + i, L.ky[vc_iy(L, i, ny, k)]);
+        if (k == 0) v += vc_bterm(P, L, 4, (size_t)j * nx + i, L.kz[vc_iz(L, i, j, 0)]);
+        if (k == nz - 1) v += vc_bterm(P, L, 5, (size_t)j * nx + i, L.kz[vc_iz(L, i, j, nz)]);
+        P.bt[c] = v * (P.h * P.h);
+    }
+}
+
+// one colour of a red-black Gauss-Seidel sweep (red = (i+j+k) even):
+// phi_c <- (b~_c + sum k_f phi_n) / d_c
+__global__ void k_vc_sweep(VcLevel L, double* phi, const double* bt, int colour, const Ctl* ctl)
+{
+    if (ctl != nullptr && ctl->done) return;
+    const int nx = L.nx, ny = L.ny;
+    const int hx = (nx + 1) / 2;                      // cells of one colour per row (at most)
+    const size_t total = (size_t)hx * ny * L.nz;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int m = (int)(t % hx);
+        const size_t row = t / hx;
+        const int j = (int)(row % ny), k = (int)(row / ny);
+        const int i = 2 * m + ((j + k + colour) & 1);
+        if (i >= nx) continue;
+        double d, sum;
+        vc_row(L, phi, i, j, k, d, sum);
+        const size_t c = ((size_t)k * ny + j) * nx + i;
+        phi[c] = (bt[c] + sum) / d;
+    }
+}
+
+// residual of the 8 children of every coarse cell, averaged into the coarse
+// b-tilde (b~_{l+1} = (1/4) sum of the children's r~ = r / s_l, since
+// s_{l+1} = s_l / 2 and R averages), and the coarse initial guess set to zero
+__global__ void k_vc_restrict(VcLevel L, const double* phi, const double* bt, double* bc, double* phic,
+                              const Ctl* ctl)
+{
+    if (ctl != nullptr && ctl->done) return;
+    const int cnx = L.nx / 2, cny = L.ny / 2, cnz = L.nz / 2;
+    const size_t nc = (size_t)cnx * cny * cnz;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nc; t += (size_t)gridDim.x * blockDim.x) {
+        const int I = (int)(t % cnx), J = (int)((t / cnx) % cny), K = (int)(t / ((size_t)cnx * cny));
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
+            const size_t c = ((size_t)k * L.ny + j) * L.nx + i;
+            double d, sum;
+            vc_row(L, phi, i, j, k, d, sum);
+            acc += bt[c] - (d * phi[c] - sum);
+        }
+        bc[t] = 0.25 * acc;
+        phic[t] = 0.0;
+    }
+}
+
+// nearest-neighbour prolongation with the magnified correction
+__global__ void k_vc_prolong(double* phi, const double* ec, int nx, int ny, int nz, double omega, const Ctl* ctl)
+{
+    if (ctl != nullptr && ctl->done) return;
+    const int cnx = nx / 2, cny = ny / 2;
+    const size_t n = (size_t)nx * ny * nz;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+        phi[c] += omega * ec[((size_t)(k >> 1) * cny + (j >> 1)) * cnx + (i >> 1)];
+    }
+}
+
+// finest residual norm (and ||b~||) with the last-block finalisation;
+// r_out (nullable) receives the residual times rscale
+constexpr int kVcNormThreads = 256;
+__global__ __launch_bounds__(kVcNormThreads) void k_vc_norm(VcLevel L, const double* phi, const double* bt,
+                                                           double* r_out, double rscale, double* partials, Ctl* ctl,
+                                                           int fin, int cycle)
+{
+    if (fin == FIN_CYCLE && ctl->done) return;
+    const int nx = L.nx, ny = L.ny;
+    const size_t n = (size_t)nx * ny * L.nz;
+    double r2 = 0.0, b2 = 0.0;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+        double d, sum;
+        vc_row(L, phi, i, j, k, d, sum);
+        const double r = bt[c] - (d * phi[c] - sum);
+        r2 += r * r;
+        b2 += bt[c] * bt[c];
+        if (r_out != nullptr) r_out[c] = r * rscale;
+    }
+    finish_norm<kVcNormThreads>(r2, b2, partials, ctl, fin, cycle, (int)gridDim.x, (int)blockIdx.x);
+}
+
+// coarsest level: conjugate gradients by one workgroup (Sec. 5.3) on the
+// stored stencil, from x = 0 until ||r|| <= rtol ||b|| or maxit; vectors in LDS
+constexpr int kVcCgThreads = 512;
+__global__ __launch_bounds__(kVcCgThreads) void k_vc_cg(VcLevel L, const double* b, double* x_out, double rtol,
+                                                       int maxit, const Ctl* ctl)
+{
+    if (ctl != nullptr && ctl->done) return;
+    extern __shared__ double vcg[];
+    const int n = L.nx * L.ny * L.nz;
+    double* x = vcg;
+    double* r = x + n;
+    double* p = r + n;
+    double* q = p + n;
+    const int tid = threadIdx.x;
+    double rr = 0.0;
+    for (int c = tid; c < n; c += kVcCgThreads) {
+        x[c] = 0.0;
+        r[c] = b[c];
+        p[c] = b[c];
+        rr += b[c] * b[c];
+    }
+    rr = block_sum_d<kVcCgThreads>(rr);
+    const double bn = sqrt(rr);
+    if (bn > 0.0) {
+        for (int it = 0; it < maxit; ++it) {
+            double pq = 0.0;
+            for (int c = tid; c < n; c += kVcCgThreads) {
+                const int i = c % L.nx, j = (c / L.nx) % L.ny, k = c / (L.nx * L.ny);
+                double d, sum;
+                vc_row(L, p, i, j, k, d, sum);
+                q[c] = d * p[c] - sum;
+                pq += p[c] * q[c];
+            }
+            pq = block_sum_d<kVcCgThreads>(pq);
+            const double alpha = rr / pq;
+            double rn = 0.0;
+            for (int c = tid; c < n; c += kVcCgThreads) {
+                x[c] += alpha * p[c];
+                r[c] -= alpha * q[c];
+                rn += r[c] * r[c];
+            }
+            rn = block_sum_d<kVcCgThreads>(rn);
+            if (sqrt(rn) <= rtol * bn) break;
+            const double beta = rn / rr;
+            rr = rn;
+            for (int c = tid; c < n; c += kVcCgThreads) p[c] = r[c] + beta * p[c];
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < n; c += kVcCgThreads) x_out[c] = x[c];
+}
+
 }  // namespace ccmg

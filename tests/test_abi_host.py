@@ -103,6 +103,23 @@ def test_calls_without_workspace_fail_cleanly():
     L.ccmg_destroy(hd)
 
 
+def test_variable_permittivity_options():
+    rc, _ = create((32, 32, 32), ZD, variable_eps=2)
+    assert rc == pkg.E_ARG
+    rc, _ = create((32, 32, 32), ZD, variable_eps=1, precision=pkg.FP32_IR)
+    assert rc == pkg.E_ARG
+    L = pkg.lib()
+    rc, h0 = create((64, 64, 64), ZD, levels=4)
+    rc1, h1 = create((64, 64, 64), ZD, levels=4, variable_eps=1)
+    assert rc == 0 and rc1 == 0
+    n = 64 ** 3
+    # three face arrays per level
+    assert L.ccmg_workspace_bytes(h1) - L.ccmg_workspace_bytes(h0) >= 8 * 3 * (n + n // 8 + n // 64 + n // 512)
+    assert L.ccmg_set_permittivity(h1, None) == pkg.E_STATE   # no workspace yet
+    L.ccmg_destroy(h0)
+    L.ccmg_destroy(h1)
+
+
 @pytest.mark.parametrize("subsample,mode", [(0, 0), (9, 0), (2, 2), (3, -1)])
 def test_subsampled_deposition_rejects_arguments(subsample, mode):
     """Checked before any device access (n = 0 spheres)."""
@@ -122,4 +139,4 @@ def test_defaults():
     pkg.lib().ccmg_default_options(ctypes.byref(o))
     assert (o.nu1, o.nu2, o.omega, o.precision, o.levels) == (2, 2, 2.0, 0, 0)
     assert o.cg_rtol == 1e-13
-    assert (o.fuse_sweeps, o.bottom_cells) == (2, 4096)
+    assert (o.fuse_sweeps, o.bottom_cells, o.variable_eps) == (2, 4096, 0)

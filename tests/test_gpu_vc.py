@@ -1,0 +1,152 @@
+"""GPU parity of the variable-permittivity solver (-div(eps grad phi) = rho,
+Galerkin-coarsened stored stencils; Sec. 3, Sec. 5.3) against the oracle.
+
+Bars as for the constant-coefficient solver: per-cycle iterates and solves
+within 1e-12 of the field's magnitude with the same cycle count, residuals
+within 1e-12 of ||b||, and at full size the oracle's own residual of the GPU
+solution below the tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1410_6609_amd as pkg
+import workloads as W
+from workloads import DIRICHLET as D, NEUMANN as N
+
+from test_gpu_parity import CASES, DEV, ids, log_case, rhs, to_dev
+
+pytestmark = pytest.mark.gpu
+
+VC_CASES = [CASES[1], CASES[3], CASES[4], ((64, 64, 64), 4, (N, N, N, N, D, D), (0, 0, 0, 0, 0.0, 1.0))]
+
+
+def lognormal_eps(shape, seed, sigma=1.2):
+    nx, ny, nz = shape
+    return np.exp(np.random.default_rng(seed).normal(0.0, sigma, (nz, ny, nx)))
+
+
+def sphere_eps(shape, sph, inside=2.5, outside=78.5):
+    nx, ny, nz = shape
+    Z, Y, X = np.meshgrid(*[np.arange(n) + 0.5 for n in (nz, ny, nx)], indexing="ij")
+    eps = np.full((nz, ny, nx), outside)
+    for c, r in zip(sph.centers, sph.radii):
+        lo = np.maximum(np.floor(c - r - 1).astype(int), 0)
+        hi = np.minimum(np.ceil(c + r + 1).astype(int), [nx, ny, nz])
+        sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+        inb = (X[sl] - c[0]) ** 2 + (Y[sl] - c[1]) ** 2 + (Z[sl] - c[2]) ** 2 <= r * r
+        eps[sl][inb] = inside
+    return eps
+
+
+def vc_solver(shape, levels, kinds, values, h, eps, **opt):
+    s = pkg.Solver(shape, h, list(zip(kinds, values)), pkg.Options(levels=levels, variable_eps=1, **opt), device=DEV)
+    s.set_permittivity(to_dev(eps))
+    return s
+
+
+@pytest.mark.parametrize("case", VC_CASES, ids=ids)
+def test_vc_vcycle_parity_per_cycle(case):
+    shape, levels, kinds, values = case
+    log_case("vc vcycle", shape)
+    h = 1.0 / shape[0]
+    eps = lognormal_eps(shape, 3)
+    s = vc_solver(shape, levels, kinds, values, h, eps)
+    f = rhs(shape, 5)
+    fd = to_dev(f)
+    phi = s.zeros()
+    b = oracle.vc_fold(f, h, kinds, values, oracle.vc_faces(eps))
+    ref = np.zeros_like(f)
+    for k in range(1, 4):
+        rel = s.vcycle(phi, fd)
+        ref, hist, _ = oracle.vc_solve(b, h, kinds, levels, eps, rtol=0.0, max_cycles=1, phi0=ref)
+        assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max(), k
+        assert abs(rel - hist[-1]) <= 1e-9 * hist[-1], (k, rel, hist[-1])
+
+
+@pytest.mark.parametrize("case", VC_CASES, ids=ids)
+def test_vc_solve_parity(case):
+    shape, levels, kinds, values = case
+    log_case("vc solve", shape)
+    h = 1.0 / shape[0]
+    eps = lognormal_eps(shape, 4)
+    s = vc_solver(shape, levels, kinds, values, h, eps)
+    f = rhs(shape, 6)
+    phi, st = s.solve(to_dev(f), rtol=1e-10)
+    b = oracle.vc_fold(f, h, kinds, values, oracle.vc_faces(eps))
+    ref, hist, ost = oracle.vc_solve(b, h, kinds, levels, eps, rtol=1e-10)
+    assert ost == 0 and st.rel_res < 1e-10 and st.cycles == len(hist) - 1
+    assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_vc_jumping_permittivity_spheres():
+    """Dielectric spheres (eps 2.5) in a fluid (eps 78.5) carrying the charges."""
+    w = W.C2.scaled((64, 64, 64), levels=4, n_spheres=30)
+    w = W.Workload(**{**w.__dict__, "r_lo": 3.0, "r_hi": 6.0})
+    sph = W.workload_spheres(w)
+    eps = sphere_eps(w.shape, sph)
+    s = vc_solver(w.shape, w.levels, w.kinds, w.values, w.h, eps)
+    f = s.deposit(to_dev(sph.centers), to_dev(sph.radii), to_dev(sph.charges), 1.0)
+    phi, st = s.solve(f, rtol=1e-10)
+    fr, _ = oracle.deposit(w.shape, w.h, sph.centers, sph.radii, sph.charges)
+    b = oracle.vc_fold(fr, w.h, w.kinds, w.values, oracle.vc_faces(eps))
+    ref, hist, _ = oracle.vc_solve(b, w.h, w.kinds, w.levels, eps, rtol=1e-10)
+    assert st.cycles == len(hist) - 1
+    assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_vc_constant_permittivity_matches_constant_solver():
+    shape, levels, kinds, values = CASES[3]
+    h = 1.0 / shape[0]
+    c = 3.0
+    f = rhs(shape, 8)
+    s = vc_solver(shape, levels, kinds, values, h, np.full((shape[2], shape[1], shape[0]), c))
+    phi, st = s.solve(to_dev(f), rtol=1e-11)
+    s0 = pkg.Solver(shape, h, list(zip(kinds, [v for v in values])), pkg.Options(levels=levels), device=DEV)
+    # -c Lap phi = f with the same boundary values  <=>  -Lap phi = f / c
+    phi0, _ = s0.solve(to_dev(f / c), rtol=1e-11)
+    assert np.abs(phi.cpu().numpy() - phi0.cpu().numpy()).max() <= 1e-9 * np.abs(phi0.cpu().numpy()).max()
+    # back to the constant operator
+    s.set_permittivity(None)
+    phi2, _ = s.solve(to_dev(f / c), rtol=1e-11)
+    assert torch.equal(phi2, phi0)
+
+
+def test_vc_residual_smooth_and_adjoint():
+    shape, levels, kinds, values = CASES[1]
+    h = 1.0 / shape[0]
+    eps = lognormal_eps(shape, 9)
+    k = oracle.vc_faces(eps)
+    s = vc_solver(shape, levels, kinds, values, h, eps)
+    f, phi = rhs(shape, 10), rhs(shape, 11)
+    b = oracle.vc_fold(f, h, kinds, values, k)
+    r, rel = s.residual(to_dev(phi), to_dev(f))
+    r_ref = b - oracle.vc_apply(phi, h, kinds, k)
+    assert np.abs(r.cpu().numpy() - r_ref).max() <= 1e-12 * np.abs(b).max()
+    assert abs(rel - np.linalg.norm(r_ref) / np.linalg.norm(b)) <= 1e-12
+    sm = s.smooth(to_dev(phi), to_dev(f), sweeps=2).cpu().numpy()
+    sm_ref = oracle.vc_rbgs_sweep(phi, b, h, kinds, k, sweeps=2)
+    assert np.abs(sm - sm_ref).max() <= 1e-12 * np.abs(sm_ref).max()
+    g = rhs(shape, 12)
+    lam, _, drho, st = s.adjoint(to_dev(g), eps=1.0, want_drho=True, rtol=1e-10)
+    lref, hist, _ = oracle.vc_solve(g, h, kinds, levels, eps, rtol=1e-10)
+    assert st.cycles == len(hist) - 1
+    assert np.abs(lam.cpu().numpy() - lref).max() <= 1e-12 * np.abs(lref).max()
+
+
+def test_vc_full_size_spheres_256():
+    """256^3 with the 200 spheres of the FP64 benchmark as dielectric particles
+    (eps 2.5 in a fluid of eps 78.5): the oracle's own residual of the GPU
+    solution is below the tolerance."""
+    w = W.C2
+    sph = W.workload_spheres(w)
+    log_case("vc 256", w.shape)
+    eps = sphere_eps(w.shape, sph)
+    s = vc_solver(w.shape, w.levels, w.kinds, w.values, w.h, eps)
+    f = s.deposit(to_dev(sph.centers), to_dev(sph.radii), to_dev(sph.charges), 1.0)
+    phi, st = s.solve(f, rtol=1e-10)
+    assert st.rel_res < 1e-10 and st.cycles <= 20
+    k = oracle.vc_faces(eps)
+    b = oracle.vc_fold(f.cpu().numpy(), w.h, w.kinds, w.values, k)
+    r = b - oracle.vc_apply(phi.cpu().numpy(), w.h, w.kinds, k)
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 1.0001e-10
