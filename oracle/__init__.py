@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
             "or_vc_rbgs_sweep": ([I, I, I, D, I, ip, dp, dp, dp, dp, dp, I], None),
             "or_vc_fold": ([I, I, I, D, ip, dp, ctypes.POINTER(ctypes.c_void_p), dp, dp, dp, dp, dp], None),
             "or_vc_solve": ([I, I, I, D, ip, I, I, I, D, D, I, dp, dp, dp, D, I, dp, ip], I),
+            "or_coulomb_adjoint": ([I, I, I, D, ip, dp, ctypes.POINTER(ctypes.c_void_p), dp, I, dp, dp, dp, I, I,
+                                    dp, dp, dp], None),
             "or_solve": ([I, I, I, D, ip, I, I, I, D, D, I, dp, dp, D, I, dp, ip], I),
             "or_solve_ir": ([I, I, I, D, ip, I, I, I, D, D, I, I, dp, dp, D, I, dp, ip], I),
         }
@@ -228,6 +230,21 @@ def coulomb(phi, h, kinds, values, centers, radii, q, subsample: int = 1, mode: 
     lib().or_coulomb(nx, ny, nz, h, _kinds(kinds), vals, ptrs, _dp(phi), radii.shape[0], _dp(centers), _dp(radii),
                      _dp(q), subsample, mode, _dp(out))
     return out
+
+
+def coulomb_adjoint(phi, h, kinds, values, centers, radii, q, gF, subsample: int = 1, mode: int = 0, faces=None):
+    """(mu = dL/dphi field, direct dL/dq_s at fixed phi) for a loss with dL/dF = gF [n, 3]."""
+    phi = _f64(phi)
+    nx, ny, nz = _shape(phi)
+    centers, radii, q = _f64(centers).reshape(-1, 3), _f64(radii), _f64(q)
+    gF = _f64(gF).reshape(-1, 3)
+    mu = np.empty_like(phi)
+    direct = np.zeros(radii.shape[0])
+    keep, ptrs = _faces((nx, ny, nz), faces)
+    vals = (ctypes.c_double * 6)(*[float(v) for v in values])
+    lib().or_coulomb_adjoint(nx, ny, nz, h, _kinds(kinds), vals, ptrs, _dp(phi), radii.shape[0], _dp(centers),
+                             _dp(radii), _dp(q), subsample, mode, _dp(gF), _dp(mu), _dp(direct))
+    return mu, direct
 
 
 def deposit(shape, h, centers, radii, q, eps: float = 1.0):

@@ -698,6 +698,86 @@ void or_coulomb(int nx, int ny, int nz, double h, const int* kinds, const double
     }
 }
 
+/* Adjoint of the force for a loss L(F) with gF[3s..3s+2] = dL/dF_s.  The force
+ * is affine in phi: F_s = -h^3 (q_s / norm_s) sum_b w_{s,b} (G phi)_b, G the
+ * gradient above (its boundary ghosts add constants).  Outputs:
+ *   mu = dL/dphi = sum_s -h^3 (q_s / norm_s) G_lin^T (w_s (x) gF_s), a field
+ *        (G_lin: G without the boundary constants);
+ *   direct[s] = gF_s . F_s / q_s computed without dividing, i.e. the
+ *        derivative of L through the prefactor q_s at fixed phi.
+ * dL/dq then adds the charge gradient of the deposition for lambda = A^-1 mu. */
+static void scatter_gradient_transpose(const or_level* L, const int* kinds, double h, int i, int j, int k,
+                                       const double v[3], double* mu)
+{
+    const int inner = i > 0 && i < L->nx - 1 && j > 0 && j < L->ny - 1 && k > 0 && k < L->nz - 1;
+    if (inner) {
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int nnz = (dx != 0) + (dy != 0) + (dz != 0);
+                    if (nnz == 0 || nnz == 3) continue;
+                    const double w = nnz == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
+                    const double cv = (double)dx * v[0] + (double)dy * v[1] + (double)dz * v[2];
+                    mu[IDX(L, i + dx, j + dy, k + dz)] += 3.0 * w * cv / h;
+                }
+        return;
+    }
+    /* D3Q7: component a is (phi(+) - phi(-)) / (2h); a ghost is a phi_b + const
+     * with a = -1 (Dirichlet) or +1 (Neumann) */
+    const int n[3] = {L->nx, L->ny, L->nz};
+    const int c[3] = {i, j, k};
+    for (int a = 0; a < 3; ++a) {
+        for (int side = -1; side <= 1; side += 2) {
+            int p[3] = {i, j, k};
+            p[a] += side;
+            const double coef = (double)side * v[a] / (2.0 * h);
+            if (p[a] >= 0 && p[a] < n[a]) {
+                mu[IDX(L, p[0], p[1], p[2])] += coef;
+            } else {
+                const int fc = 2 * a + (side > 0 ? 1 : 0);
+                const double ga = kinds[fc] == OR_DIRICHLET ? -1.0 : 1.0;
+                mu[IDX(L, c[0], c[1], c[2])] += coef * ga;
+            }
+        }
+    }
+}
+
+void or_coulomb_adjoint(int nx, int ny, int nz, double h, const int* kinds, const double* values,
+                        const double* const* face, const double* phi, int n, const double* centers,
+                        const double* radii, const double* q, int sf, int mode, const double* gF, double* mu,
+                        double* direct)
+{
+    const or_level L = make_level(nx, ny, nz, h, 0, kinds);
+    memset(mu, 0, or_cells(&L) * sizeof(double));
+    for (int s = 0; s < n; ++s) {
+        const double* c = centers + 3 * (size_t)s;
+        const double R = radii[s];
+        direct[s] = 0.0;
+        const double W = sphere_weight(nx, ny, nz, h, c, R, sf);
+        if (W == 0.0) continue;
+        const double norm = sphere_norm(mode, 1.0, W, R, h);
+        const double pre = -(h * h * h) / norm;
+        int ilo, ihi, jlo, jhi, klo, khi;
+        axis_range(c[0], R, h, nx, &ilo, &ihi);
+        axis_range(c[1], R, h, ny, &jlo, &jhi);
+        axis_range(c[2], R, h, nz, &klo, &khi);
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int k = klo; k <= khi; ++k)
+            for (int j = jlo; j <= jhi; ++j)
+                for (int i = ilo; i <= ihi; ++i) {
+                    const double w = cell_ratio(i, j, k, sf, h, c, R);
+                    if (w == 0.0) continue;
+                    double g[3];
+                    gradient_at(&L, phi, kinds, values, face, h, i, j, k, g);
+                    for (int a = 0; a < 3; ++a) acc[a] += g[a] * w;
+                    const double v[3] = {pre * q[s] * w * gF[3 * s], pre * q[s] * w * gF[3 * s + 1],
+                                         pre * q[s] * w * gF[3 * s + 2]};
+                    scatter_gradient_transpose(&L, kinds, h, i, j, k, v, mu);
+                }
+        direct[s] = pre * (acc[0] * gF[3 * s] + acc[1] * gF[3 * s + 1] + acc[2] * gF[3 * s + 2]);
+    }
+}
+
 /* Multigrid solve (Alg. 1): with rho_k = ||b - A phi_k||_2 / ||b||_2, perform
  * V-cycles while rho_k >= rtol, at most max_cycles.  b is the folded finest
  * right-hand side; phi holds the initial guess on entry.  hist[0..cycles]

@@ -152,3 +152,65 @@ def test_force_of_a_sphere_in_its_own_field_vanishes_by_symmetry(orc):
     F = orc.coulomb(phi, 1.0, (D,) * 6, (0.0,) * 6, c, r, q, subsample=2)
     g = orc.gradient(phi, 1.0, (D,) * 6, (0.0,) * 6)
     assert np.abs(F).max() <= 1e-12 * q[0] * np.abs(g).max()
+
+
+# ---- adjoint of the force ------------------------------------------------------
+def spheres_near_walls():
+    c = np.array([[6.3, 7.1, 5.2], [1.2, 8.0, 9.5], [14.6, 3.3, 14.4], [8.0, 8.0, 1.0]])
+    r = np.array([3.4, 2.6, 2.9, 2.2])
+    q = np.array([1.3, -0.7, 0.9, 2.0])
+    return c, r, q
+
+
+@pytest.mark.parametrize("kinds", [(D, D, N, N, N, N), (N, D, D, N, D, N)])
+def test_force_adjoint_is_the_transpose(orc, kinds):
+    """<mu, psi> equals sum_s gF_s . (F_s(psi) - F_s(0)) for random psi: the
+    scatter is the exact transpose of the (linear part of the) force map,
+    boundary-layer cells included."""
+    shape, h = (16, 12, 16), 0.8
+    values = (0.3, -0.2, 0.1, 0.4, -0.5, 0.2)
+    c, r, q = spheres_near_walls()
+    c, r = c * h, r * h
+    rng = np.random.default_rng(1)
+    gF = rng.standard_normal((4, 3))
+    psi = rng.standard_normal((16, 12, 16))
+    for sf, mode in ((1, 0), (2, 1), (3, 0)):
+        mu, direct = orc.coulomb_adjoint(np.zeros_like(psi), h, kinds, values, c, r, q, gF, sf, mode)
+        F1 = orc.coulomb(psi, h, kinds, values, c, r, q, sf, mode)
+        F0 = orc.coulomb(np.zeros_like(psi), h, kinds, values, c, r, q, sf, mode)
+        lhs = float(np.vdot(mu, psi))
+        rhs_ = float(np.sum(gF * (F1 - F0)))
+        assert abs(lhs - rhs_) <= 1e-12 * max(1.0, abs(rhs_))
+        # direct term at fixed phi: gF_s . F_s / q_s
+        Fp = orc.coulomb(psi, h, kinds, values, c, r, q, sf, mode)
+        _, d2 = orc.coulomb_adjoint(psi, h, kinds, values, c, r, q, gF, sf, mode)
+        assert np.allclose(d2, np.sum(gF * Fp, axis=1) / q, rtol=1e-12, atol=1e-14)
+
+
+def test_force_charge_gradient_by_finite_differences(orc):
+    """dL/dq for L = sum_s gF_s . F_s(q) through deposition, solve and force:
+    direct term + charge gradient of lambda = A^-1 mu, against central
+    differences of the full forward map (affine in every q_t... quadratic in q
+    overall, so central differences are exact up to solver tolerance)."""
+    shape, h, eps = (16, 16, 16), 1.0, 0.7
+    kinds, values = (D, D, N, N, N, N), (0.0, -2.0, 0, 0, 0, 0)
+    c, r, q = spheres_near_walls()
+    gF = np.random.default_rng(2).standard_normal((4, 3))
+    sf_d, sf_f, mode = 2, 3, 1
+
+    def forces(qv):
+        f, _ = orc.deposit_sub(shape, h, c, r, qv, eps, subsample=sf_d, mode=mode)
+        phi, _, _ = orc.solve_problem(f, h, kinds, values, 3, rtol=1e-14, max_cycles=80)
+        return orc.coulomb(phi, h, kinds, values, c, r, qv, sf_f, mode), phi
+
+    F, phi = forces(q)
+    mu, direct = orc.coulomb_adjoint(phi, h, kinds, values, c, r, q, gF, sf_f, mode)
+    lam, _, _ = orc.adjoint(mu, h, kinds, 3, rtol=1e-14, max_cycles=80)
+    grad = direct + orc.dq_sub(lam, h, c, r, eps, subsample=sf_d, mode=mode)
+    step = 1e-3
+    for t in range(4):
+        qp, qm = q.copy(), q.copy()
+        qp[t] += step
+        qm[t] -= step
+        fd = (np.sum(gF * forces(qp)[0]) - np.sum(gF * forces(qm)[0])) / (2 * step)
+        assert abs(fd - grad[t]) <= 1e-8 * max(1.0, abs(grad[t])), (t, fd, grad[t])
