@@ -185,6 +185,23 @@ int ccmg_gradient(ccmg_solver* s, const double* d_phi, double* d_grad);
 int ccmg_coulomb_force(ccmg_solver* s, const double* d_phi, int n, const double* d_centers,
                        const double* d_radii, const double* d_q, int subsample, int mode, double* d_force);
 
+/* Adjoint of the electrostatic force, for a loss L(F) with d_gF[3s..3s+2] =
+ * dL/dF_s (device, double[3n]).  The force of ccmg_coulomb_force is affine in
+ * phi; this call writes
+ *   d_mu     = dL/dphi (a field, overwritten): the transposed gradient
+ *              stencil applied to -h^3 (q_s / norm_s) w_{s,b} dL/dF_s,
+ *              summed over spheres (boundary ghosts contribute their linear
+ *              part: -phi_b Dirichlet, +phi_b Neumann);
+ *   d_direct = the derivative of L through each force's charge factor at
+ *              fixed phi, dL/dF_s . F_s / q_s (double[n]).
+ * With lambda from ccmg_adjoint_solve(d_mu), dL/dq_s = d_direct[s] + the
+ * deposition's charge gradient of lambda (ccmg_charge_gradient, with the
+ * deposition's own subsample and mode).  Arguments as ccmg_coulomb_force.
+ * Enqueued without waiting. */
+int ccmg_coulomb_adjoint(ccmg_solver* s, const double* d_phi, int n, const double* d_centers,
+                         const double* d_radii, const double* d_q, int subsample, int mode, const double* d_gF,
+                         double* d_mu, double* d_direct);
+
 /* Cell-wise permittivity (extension for discontinuous dielectricity, which
  * the paper's solver is designed for by Galerkin coarsening, Sec. 3, with
  * per-unknown stencils, Sec. 5.3).  Needs a solver created with

@@ -110,6 +110,8 @@ _SIGS = {
     "ccmg_set_face_values": ([_VP, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_gradient": ([_VP, _VP, _VP], ctypes.c_int),
     "ccmg_set_permittivity": ([_VP, _VP], ctypes.c_int),
+    "ccmg_coulomb_adjoint": ([_VP, _VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP],
+                             ctypes.c_int),
     "ccmg_coulomb_force": ([_VP, _VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_vcycle": ([_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ccmg_vcycles": ([_VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
@@ -290,6 +292,29 @@ class Solver:
                                              int(mode), _ptr(F)))
         return F
 
+    def coulomb_adjoint(self, phi: torch.Tensor, centers, radii, q, gF: torch.Tensor, subsample: int = 1,
+                        mode: int = SPREAD):
+        """(mu = dL/dphi, direct per-sphere term) for dL/dF = gF of shape (n, 3)."""
+        phi = self._field(phi, "phi")
+        c, r = self._spheres(centers, radii)
+        q = q.to(self.device, torch.float64).contiguous().reshape(-1)
+        gF = gF.to(self.device, torch.float64).contiguous().reshape(-1, 3)
+        n = r.shape[0]
+        mu = self.zeros()
+        direct = torch.zeros(n, dtype=torch.float64, device=self.device)
+        self._bind_stream()
+        self._check(lib().ccmg_coulomb_adjoint(self._h, _ptr(phi), n, _ptr(c), _ptr(r), _ptr(q), int(subsample),
+                                               int(mode), _ptr(gF), _ptr(mu), _ptr(direct)))
+        return mu, direct
+
+    def force_charge_gradient(self, phi: torch.Tensor, centers, radii, q, gF: torch.Tensor, eps: float = 1.0,
+                              force_subsample: int = 1, force_mode: int = SPREAD, deposit_subsample: int = 1,
+                              deposit_mode: int = SPREAD, rtol: float = 1e-10, max_cycles: int = 100):
+        """dL/dq for a loss on the forces computed from phi = A^-1 b(deposit(q))."""
+        mu, direct = self.coulomb_adjoint(phi, centers, radii, q, gF, force_subsample, force_mode)
+        lam, _, _, _ = self.adjoint(mu, rtol=rtol, max_cycles=max_cycles)
+        return direct + self.charge_gradient(lam, centers, radii, eps, deposit_subsample, deposit_mode)
+
     def set_permittivity(self, eps: Optional[torch.Tensor]) -> None:
         """Cell-wise permittivity (None: back to the constant operator); needs
         Options(variable_eps=1).  Afterwards solves take f = rho."""
@@ -431,6 +456,30 @@ class PoissonFn(torch.autograd.Function):
         g = grad_phi.contiguous().to(torch.float64)
         _, dq, _, _ = ctx.solver.adjoint(g, centers, radii, ctx.eps, ctx.rtol, ctx.max_cycles,
                                          subsample=ctx.subsample, mode=ctx.mode)
+        return dq, None, None, None, None, None, None, None, None
+
+
+class CoulombForceFn(torch.autograd.Function):
+    """Forces on charged spheres: q -> deposition -> phi = A^-1 b -> F (n, 3);
+    backward by the force adjoint, one adjoint solve and the deposition's
+    charge gradient."""
+
+    @staticmethod
+    def forward(ctx, q, centers, radii, solver: Solver, eps: float = 1.0, rtol: float = 1e-10,
+                max_cycles: int = 100, subsample: int = 1, mode: int = SPREAD):
+        f = solver.deposit(centers, radii, q, eps, subsample=subsample, mode=mode)
+        phi, _ = solver.solve(f, rtol=rtol, max_cycles=max_cycles)
+        F = solver.coulomb_force(phi, centers, radii, q, subsample=subsample, mode=mode)
+        ctx.solver, ctx.eps, ctx.rtol, ctx.max_cycles = solver, eps, rtol, max_cycles
+        ctx.subsample, ctx.mode = subsample, mode
+        ctx.save_for_backward(q, centers, radii, phi)
+        return F
+
+    @staticmethod
+    def backward(ctx, grad_F):
+        q, centers, radii, phi = ctx.saved_tensors
+        dq = ctx.solver.force_charge_gradient(phi, centers, radii, q.detach(), grad_F, ctx.eps, ctx.subsample,
+                                              ctx.mode, ctx.subsample, ctx.mode, ctx.rtol, ctx.max_cycles)
         return dq, None, None, None, None, None, None, None, None
 
 

@@ -918,6 +918,20 @@ struct Coulomb {
     static void run(A... a) { launch_coulomb<SF>(a...); }
 };
 
+template <int SF>
+void launch_coulomb_adjoint(ccmg_solver* s, const double* phi, GradBc B, int n, const double* c, const double* r,
+                            const double* q, int mode, const double* gF, double* mu, double* direct)
+{
+    hipLaunchKernelGGL((k_coulomb_adjoint<SF>), dim3(n), dim3(kSphereThreads), 0, s->stream, phi, B, c, r, q, mode, gF,
+                       mu, direct);
+}
+
+template <int SF>
+struct CoulombAdj {
+    template <typename... A>
+    static void run(A... a) { launch_coulomb_adjoint<SF>(a...); }
+};
+
 GradBc grad_bc(const ccmg_solver* s)
 {
     GradBc B{};
@@ -1174,6 +1188,28 @@ int ccmg_coulomb_force(ccmg_solver* s, const double* d_phi, int n, const double*
     NEED_DEV(s, d_q, "d_q");
     NEED_DEV(s, d_force, "d_force");
     by_subsample<Coulomb>(subsample, s, d_phi, grad_bc(s), n, d_centers, d_radii, d_q, mode, d_force);
+    LAUNCHCHK(s);
+    return CCMG_OK;
+}
+
+int ccmg_coulomb_adjoint(ccmg_solver* s, const double* d_phi, int n, const double* d_centers, const double* d_radii,
+                         const double* d_q, int subsample, int mode, const double* d_gF, double* d_mu, double* d_direct)
+{
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    if ((rc = check_spheres(s, n, d_centers, d_radii, subsample, mode))) return rc;
+    NEED_DEV(s, d_mu, "d_mu");
+    const size_t n0 = s->lv[0].n;
+    hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(n0)), dim3(256), 0, s->stream, d_mu, n0, 0.0);
+    if (n > 0) {
+        NEED_DEV(s, d_phi, "d_phi");
+        NEED_DEV(s, d_q, "d_q");
+        NEED_DEV(s, d_gF, "d_gF");
+        NEED_DEV(s, d_direct, "d_direct");
+        by_subsample<CoulombAdj>(subsample, s, d_phi, grad_bc(s), n, d_centers, d_radii, d_q, mode, d_gF, d_mu,
+                                 d_direct);
+    }
     LAUNCHCHK(s);
     return CCMG_OK;
 }

@@ -1498,6 +1498,104 @@ __global__ __launch_bounds__(kSphereThreads) void k_coulomb(const double* phi, G
     }
 }
 
+// Adjoint of the force for a loss with dL/dF_s = gF_s: mu += G_lin^T of
+// -h^3 (q_s / norm_s) w_b gF_s at every overlapped cell (the transposed
+// D3Q19 / boundary-layer D3Q7 stencil, ghosts contributing their linear part
+// -phi_b (Dirichlet) or +phi_b (Neumann)), and direct[s] = gF_s . F_s / q_s.
+__device__ __forceinline__ void scatter_grad_t(const GradBc& B, int i, int j, int k, double vx, double vy,
+                                               double vz, double* mu)
+{
+    const size_t sy = (size_t)B.nx, sz = (size_t)B.nx * B.ny;
+    const size_t c = (size_t)k * sz + (size_t)j * sy + i;
+    if (i > 0 && i < B.nx - 1 && j > 0 && j < B.ny - 1 && k > 0 && k < B.nz - 1) {
+        const double s = 3.0 / B.h;
+        const double ax = s * vx * (1.0 / 18.0), ay = s * vy * (1.0 / 18.0), az = s * vz * (1.0 / 18.0);
+        atomicAdd(&mu[c + 1], ax);
+        atomicAdd(&mu[c - 1], -ax);
+        atomicAdd(&mu[c + sy], ay);
+        atomicAdd(&mu[c - sy], -ay);
+        atomicAdd(&mu[c + sz], az);
+        atomicAdd(&mu[c - sz], -az);
+        const double d = s * (1.0 / 36.0);
+        atomicAdd(&mu[c + 1 + sy], d * (vx + vy));
+        atomicAdd(&mu[c - 1 - sy], -d * (vx + vy));
+        atomicAdd(&mu[c + 1 - sy], d * (vx - vy));
+        atomicAdd(&mu[c - 1 + sy], -d * (vx - vy));
+        atomicAdd(&mu[c + 1 + sz], d * (vx + vz));
+        atomicAdd(&mu[c - 1 - sz], -d * (vx + vz));
+        atomicAdd(&mu[c + 1 - sz], d * (vx - vz));
+        atomicAdd(&mu[c - 1 + sz], -d * (vx - vz));
+        atomicAdd(&mu[c + sy + sz], d * (vy + vz));
+        atomicAdd(&mu[c - sy - sz], -d * (vy + vz));
+        atomicAdd(&mu[c + sy - sz], d * (vy - vz));
+        atomicAdd(&mu[c - sy + sz], -d * (vy - vz));
+        return;
+    }
+    const double inv2h = 1.0 / (2.0 * B.h);
+    const double v[3] = {vx, vy, vz};
+    const int pos[3] = {i, j, k};
+    const int n[3] = {B.nx, B.ny, B.nz};
+    const size_t st[3] = {1, sy, sz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double cf = v[a] * inv2h;
+        if (pos[a] + 1 < n[a]) atomicAdd(&mu[c + st[a]], cf);
+        else atomicAdd(&mu[c], B.dirichlet[2 * a + 1] ? -cf : cf);
+        if (pos[a] - 1 >= 0) atomicAdd(&mu[c - st[a]], -cf);
+        else atomicAdd(&mu[c], B.dirichlet[2 * a] ? cf : -cf);
+    }
+}
+
+template <int SF>
+__global__ __launch_bounds__(kSphereThreads) void k_coulomb_adjoint(const double* phi, GradBc B,
+                                                                   const double* centers, const double* radii,
+                                                                   const double* q, int mode, const double* gF,
+                                                                   double* mu, double* direct)
+{
+#pragma clang fp contract(off)
+    const int s = blockIdx.x;
+    const double cx = centers[3 * s], cy = centers[3 * s + 1], cz = centers[3 * s + 2], R = radii[s];
+    const double R2 = R * R, h = B.h;
+    Box X;
+    ball_box(cx, R, h, B.nx, X.i0, X.i1);
+    ball_box(cy, R, h, B.ny, X.j0, X.j1);
+    ball_box(cz, R, h, B.nz, X.k0, X.k1);
+    const int bx = X.i1 - X.i0 + 1, by = X.j1 - X.j0 + 1, bz = X.k1 - X.k0 + 1;
+    const long long nbox = (bx > 0 && by > 0 && bz > 0) ? (long long)bx * by * bz : 0;
+    // pass 1: W_s (the scatter needs the normalisation)
+    double cnt = 0.0;
+    for (long long c = threadIdx.x; c < nbox; c += kSphereThreads) {
+        const int i = X.i0 + (int)(c % bx), j = X.j0 + (int)((c / bx) % by), k = X.k0 + (int)(c / ((long long)bx * by));
+        cnt += (double)sub_cells_in_ball<SF>(i, j, k, h, cx, cy, cz, R2);
+    }
+    const double W = block_sum_d<kSphereThreads>(cnt) / (double)(SF * SF * SF);
+    if (W == 0.0) {
+        if (threadIdx.x == 0) direct[s] = 0.0;
+        return;
+    }
+    const double pre = -(h * h * h) / sphere_norm(mode, 1.0, W, R, h);
+    const double g0 = gF[3 * s], g1 = gF[3 * s + 1], g2 = gF[3 * s + 2], qs = q[s];
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (long long c = threadIdx.x; c < nbox; c += kSphereThreads) {
+        const int i = X.i0 + (int)(c % bx), j = X.j0 + (int)((c / bx) % by), k = X.k0 + (int)(c / ((long long)bx * by));
+        const int m = sub_cells_in_ball<SF>(i, j, k, h, cx, cy, cz, R2);
+        if (m > 0) {
+            const double w = (double)m / (double)(SF * SF * SF);
+            double gx, gy, gz;
+            grad_at(phi, B, i, j, k, gx, gy, gz);
+            ax += gx * w;
+            ay += gy * w;
+            az += gz * w;
+            const double f = pre * qs * w;
+            scatter_grad_t(B, i, j, k, f * g0, f * g1, f * g2, mu);
+        }
+    }
+    ax = block_sum_d<kSphereThreads>(ax);
+    ay = block_sum_d<kSphereThreads>(ay);
+    az = block_sum_d<kSphereThreads>(az);
+    if (threadIdx.x == 0) direct[s] = pre * (ax * g0 + ay * g1 + az * g2);
+}
+
 // ---------------------------------------------------------------------------
 // Variable permittivity: -div(eps grad phi) = rho with stored face
 // coefficients (Galerkin coarsening with the cell-centred transfers, Sec. 3;

@@ -107,3 +107,56 @@ def test_scene_forces_full_size():
     assert np.abs(F[idx] - ref).max() <= 1e-12 * np.abs(ref).max()
     # the applied field dominates: every force points to the bottom plate (phi = -100 V there)
     assert (F[:, 2] < 0).all()
+
+
+# ---- adjoint of the force --------------------------------------------------------
+@pytest.mark.parametrize("sf,mode", [(1, pkg.SPREAD), (2, pkg.VOLUME), (3, pkg.SPREAD)])
+def test_coulomb_adjoint_parity(sf, mode):
+    log_case("coulomb adjoint", sf, mode)
+    w, c, r, q = sphere_set(seed=93)
+    s = pkg.Solver(w.shape, w.h, list(zip(w.kinds, w.values)), pkg.Options(levels=w.levels), device=DEV)
+    phi = rhs(w.shape, 53)
+    gF = np.random.default_rng(94).standard_normal((len(r), 3))
+    mu, direct = s.coulomb_adjoint(to_dev(phi), to_dev(c), to_dev(r), to_dev(q), to_dev(gF), sf, mode)
+    mu_ref, d_ref = oracle.coulomb_adjoint(phi, w.h, w.kinds, w.values, c, r, q, gF, sf, mode)
+    assert np.abs(mu.cpu().numpy() - mu_ref).max() <= 1e-12 * np.abs(mu_ref).max()
+    assert np.abs(direct.cpu().numpy() - d_ref).max() <= 1e-12 * np.abs(d_ref).max()
+
+
+def test_coulomb_force_autograd_against_oracle_and_finite_differences():
+    """CoulombForceFn: q -> F through deposition (s_f = 2, q/V density), solve
+    and force.  Backward against the oracle's composite gradient, and against
+    central differences of the GPU forward map with a fixed cycle count (the
+    map is quadratic in q, so the differences are exact up to rounding)."""
+    w = W.C4.scaled((64, 64, 64), levels=4, n_spheres=12)
+    w = W.Workload(**{**w.__dict__, "r_lo": 3.0, "r_hi": 5.0, "kinds": (D, D, N, N, N, N),
+                      "values": (0.0, -1.0, 0, 0, 0, 0)})
+    sph = W.workload_spheres(w)
+    s = pkg.Solver(w.shape, w.h, list(zip(w.kinds, w.values)), pkg.Options(levels=w.levels), device=DEV)
+    c, r = to_dev(sph.centers), to_dev(sph.radii)
+    gF = np.random.default_rng(95).standard_normal((sph.n, 3))
+    qg = to_dev(sph.charges).requires_grad_(True)
+    F = pkg.CoulombForceFn.apply(qg, c, r, s, 0.9, 1e-12, 100, 2, pkg.VOLUME)
+    (F * to_dev(gF)).sum().backward()
+    grad = qg.grad.cpu().numpy()
+    # oracle: direct + charge gradient of lambda = A^-1 mu
+    f_ref, _ = oracle.deposit_sub(w.shape, w.h, sph.centers, sph.radii, sph.charges, 0.9, subsample=2,
+                                  mode=pkg.VOLUME)
+    phi_ref, _, _ = oracle.solve_problem(f_ref, w.h, w.kinds, w.values, w.levels, rtol=1e-12)
+    mu, direct = oracle.coulomb_adjoint(phi_ref, w.h, w.kinds, w.values, sph.centers, sph.radii, sph.charges, gF,
+                                        2, pkg.VOLUME)
+    lam, _, _ = oracle.adjoint(mu, w.h, w.kinds, w.levels, rtol=1e-12)
+    ref = direct + oracle.dq_sub(lam, w.h, sph.centers, sph.radii, 0.9, subsample=2, mode=pkg.VOLUME)
+    assert np.abs(grad - ref).max() <= 1e-9 * np.abs(ref).max()
+    # finite differences of the GPU forward map, 30 fixed cycles
+    def loss(qv):
+        f = s.deposit(c, r, to_dev(qv), 0.9, subsample=2, mode=pkg.VOLUME)
+        phi, _ = s.solve(f, rtol=0.0, max_cycles=30, check=False)
+        return float((s.coulomb_force(phi, c, r, to_dev(qv), 2, pkg.VOLUME) * to_dev(gF)).sum())
+    step = 1e-3
+    for t in range(0, sph.n, 3):
+        qp, qm = sph.charges.copy(), sph.charges.copy()
+        qp[t] += step
+        qm[t] -= step
+        fd = (loss(qp) - loss(qm)) / (2 * step)
+        assert abs(fd - grad[t]) <= 1e-7 * max(abs(grad[t]), 1e-3 * np.abs(grad).max()), (t, fd, grad[t])
