@@ -69,7 +69,7 @@ def lib() -> ctypes.CDLL:
             "or_gradient": ([I, I, I, D, ip, dp, ctypes.POINTER(ctypes.c_void_p), dp, dp], None),
             "or_coulomb": ([I, I, I, D, ip, dp, ctypes.POINTER(ctypes.c_void_p), dp, I, dp, dp, dp, I, I, dp],
                            None),
-            "or_vc_faces": ([I, I, I, dp, dp, dp, dp], None),
+            "or_vc_faces": ([I, I, I, ip, dp, dp, dp, dp], None),
             "or_vc_coarsen": ([I, I, I, dp, dp, dp, dp, dp, dp], None),
             "or_vc_apply": ([I, I, I, D, I, ip, dp, dp, dp, dp, dp], None),
             "or_vc_rbgs_sweep": ([I, I, I, D, I, ip, dp, dp, dp, dp, dp, I], None),
@@ -339,13 +339,14 @@ def adjoint(g, h, kinds, levels, **kw):
 
 
 # ---- variable permittivity ----------------------------------------------------
-def vc_faces(eps):
+def vc_faces(eps, kinds=(0,) * 6):
     """Normalised face coefficients (x [nz][ny][nx+1], y [nz][ny+1][nx], z [nz+1][ny][nx])
-    from a cell permittivity [nz][ny][nx]: harmonic means, boundary faces the cell's value."""
+    from a cell permittivity [nz][ny][nx]: harmonic means; a boundary face takes the
+    cell's value, a periodic one the harmonic mean across the wrap."""
     eps = _f64(eps)
     nx, ny, nz = _shape(eps)
     kx, ky, kz = np.empty((nz, ny, nx + 1)), np.empty((nz, ny + 1, nx)), np.empty((nz + 1, ny, nx))
-    lib().or_vc_faces(nx, ny, nz, _dp(eps), _dp(kx), _dp(ky), _dp(kz))
+    lib().or_vc_faces(nx, ny, nz, _kinds(kinds), _dp(eps), _dp(kx), _dp(ky), _dp(kz))
     return kx, ky, kz
 
 

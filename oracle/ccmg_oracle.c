@@ -54,6 +54,8 @@
 
 #define OR_DIRICHLET 0
 #define OR_NEUMANN 1
+#define OR_PERIODIC 2   /* both faces of an axis; only the variable-permittivity
+                           operator and the gradient/force functions take it */
 #define OR_MAXLEVELS 16
 
 #define OR_OK 0
@@ -590,9 +592,21 @@ void or_dq_sub(int nx, int ny, int nz, double h, int n, const double* centers, c
  * Dirichlet extrapolates phi_0 = 2 g - phi_1, Neumann takes
  * phi_0 - phi_1 = h g_n with g_n the outward normal derivative).  The face
  * value comes from face[fc] (per cell) when given, else values[fc]. */
+static int axis_periodic(const int* kinds, int a) { return kinds[2 * a] == OR_PERIODIC; }
+
+/* indices on periodic axes taken modulo the extent (Sec. 2.4: periodic
+ * boundaries cyclically extend the domain) */
+static void wrap_periodic(const or_level* L, const int* kinds, int* i, int* j, int* k)
+{
+    if (axis_periodic(kinds, 0)) *i = (*i + L->nx) % L->nx;
+    if (axis_periodic(kinds, 1)) *j = (*j + L->ny) % L->ny;
+    if (axis_periodic(kinds, 2)) *k = (*k + L->nz) % L->nz;
+}
+
 static double phi_or_ghost(const or_level* L, const double* phi, const int* kinds, const double* values,
                            const double* const* face, double h, int i, int j, int k)
 {
+    wrap_periodic(L, kinds, &i, &j, &k);
     int fc = -1, ii = i, jj = j, kk = k;
     if (i < 0)             { fc = 0; ii = 0; }
     else if (i >= L->nx)   { fc = 1; ii = L->nx - 1; }
@@ -612,6 +626,14 @@ static double phi_or_ghost(const or_level* L, const double* phi, const int* kind
     return kinds[fc] == OR_DIRICHLET ? 2.0 * g - in : in + h * g;
 }
 
+/* all 18 D3Q19 neighbours exist: away from every non-periodic boundary */
+static int d3q19_inside(const or_level* L, const int* kinds, int i, int j, int k)
+{
+    return (axis_periodic(kinds, 0) || (i > 0 && i < L->nx - 1)) &&
+           (axis_periodic(kinds, 1) || (j > 0 && j < L->ny - 1)) &&
+           (axis_periodic(kinds, 2) || (k > 0 && k < L->nz - 1));
+}
+
 /* Gradient of phi at cell (i,j,k), second order: the isotropic D3Q19 lattice
  * gradient grad = (1/w_1) sum_q w_q phi(x + h c_q) c_q / h over the 18
  * non-rest directions (w_1 = 1/3 the rest weight, w = 1/18 along the axes,
@@ -621,7 +643,7 @@ static double phi_or_ghost(const or_level* L, const double* phi, const int* kind
 static void gradient_at(const or_level* L, const double* phi, const int* kinds, const double* values,
                         const double* const* face, double h, int i, int j, int k, double g[3])
 {
-    const int inner = i > 0 && i < L->nx - 1 && j > 0 && j < L->ny - 1 && k > 0 && k < L->nz - 1;
+    const int inner = d3q19_inside(L, kinds, i, j, k);
     g[0] = g[1] = g[2] = 0.0;
     if (inner) {
         for (int dz = -1; dz <= 1; ++dz)
@@ -630,7 +652,9 @@ static void gradient_at(const or_level* L, const double* phi, const int* kinds, 
                     const int nnz = (dx != 0) + (dy != 0) + (dz != 0);
                     if (nnz == 0 || nnz == 3) continue;   /* rest and cube-corner directions are not in D3Q19 */
                     const double w = nnz == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
-                    const double v = phi[IDX(L, i + dx, j + dy, k + dz)];
+                    int a = i + dx, b = j + dy, c = k + dz;
+                    wrap_periodic(L, kinds, &a, &b, &c);
+                    const double v = phi[IDX(L, a, b, c)];
                     g[0] += w * v * (double)dx;
                     g[1] += w * v * (double)dy;
                     g[2] += w * v * (double)dz;
@@ -709,8 +733,7 @@ void or_coulomb(int nx, int ny, int nz, double h, const int* kinds, const double
 static void scatter_gradient_transpose(const or_level* L, const int* kinds, double h, int i, int j, int k,
                                        const double v[3], double* mu)
 {
-    const int inner = i > 0 && i < L->nx - 1 && j > 0 && j < L->ny - 1 && k > 0 && k < L->nz - 1;
-    if (inner) {
+    if (d3q19_inside(L, kinds, i, j, k)) {
         for (int dz = -1; dz <= 1; ++dz)
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx) {
@@ -718,7 +741,9 @@ static void scatter_gradient_transpose(const or_level* L, const int* kinds, doub
                     if (nnz == 0 || nnz == 3) continue;
                     const double w = nnz == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
                     const double cv = (double)dx * v[0] + (double)dy * v[1] + (double)dz * v[2];
-                    mu[IDX(L, i + dx, j + dy, k + dz)] += 3.0 * w * cv / h;
+                    int a = i + dx, b = j + dy, c = k + dz;
+                    wrap_periodic(L, kinds, &a, &b, &c);
+                    mu[IDX(L, a, b, c)] += 3.0 * w * cv / h;
                 }
         return;
     }
@@ -730,6 +755,7 @@ static void scatter_gradient_transpose(const or_level* L, const int* kinds, doub
         for (int side = -1; side <= 1; side += 2) {
             int p[3] = {i, j, k};
             p[a] += side;
+            wrap_periodic(L, kinds, &p[0], &p[1], &p[2]);
             const double coef = (double)side * v[a] / (2.0 * h);
             if (p[a] >= 0 && p[a] < n[a]) {
                 mu[IDX(L, p[0], p[1], p[2])] += coef;
@@ -915,21 +941,26 @@ static void vc_faces_from_eps(vc_level* L, const double* eps)
 {
     const int nx = L->nx, ny = L->ny, nz = L->nz;
 #define EPS(i, j, k) eps[((size_t)(k) * ny + (j)) * nx + (i)]
+    /* a periodic axis's boundary face joins cell n-1 and cell 0 (stored at 0 and n) */
+    const int px = L->kind[0] == OR_PERIODIC, py = L->kind[2] == OR_PERIODIC, pz = L->kind[4] == OR_PERIODIC;
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i <= nx; ++i)
-                VKX(L, i, j, k) = i == 0 ? EPS(0, j, k) : i == nx ? EPS(nx - 1, j, k)
-                                                             : harmonic(EPS(i - 1, j, k), EPS(i, j, k));
+                VKX(L, i, j, k) = (i == 0 || i == nx) ? (px ? harmonic(EPS(nx - 1, j, k), EPS(0, j, k))
+                                                            : EPS(i == 0 ? 0 : nx - 1, j, k))
+                                                      : harmonic(EPS(i - 1, j, k), EPS(i, j, k));
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j <= ny; ++j)
             for (int i = 0; i < nx; ++i)
-                VKY(L, i, j, k) = j == 0 ? EPS(i, 0, k) : j == ny ? EPS(i, ny - 1, k)
-                                                             : harmonic(EPS(i, j - 1, k), EPS(i, j, k));
+                VKY(L, i, j, k) = (j == 0 || j == ny) ? (py ? harmonic(EPS(i, ny - 1, k), EPS(i, 0, k))
+                                                            : EPS(i, j == 0 ? 0 : ny - 1, k))
+                                                      : harmonic(EPS(i, j - 1, k), EPS(i, j, k));
     for (int k = 0; k <= nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i)
-                VKZ(L, i, j, k) = k == 0 ? EPS(i, j, 0) : k == nz ? EPS(i, j, nz - 1)
-                                                             : harmonic(EPS(i, j, k - 1), EPS(i, j, k));
+                VKZ(L, i, j, k) = (k == 0 || k == nz) ? (pz ? harmonic(EPS(i, j, nz - 1), EPS(i, j, 0))
+                                                            : EPS(i, j, k == 0 ? 0 : nz - 1))
+                                                      : harmonic(EPS(i, j, k - 1), EPS(i, j, k));
 #undef EPS
 }
 
@@ -953,30 +984,44 @@ static void vc_coarsen(const vc_level* F, vc_level* C)
                                    VKZ(F, 2 * I, 2 * J + 1, 2 * K) + VKZ(F, 2 * I + 1, 2 * J + 1, 2 * K)) / 4.0;
 }
 
+/* contribution of a boundary face to the diagonal: Dirichlet 2k, Neumann 0,
+ * periodic k (an interior face to the cell on the opposite side) */
+static double vc_bdiag(int kind, double kf)
+{
+    return kind == OR_DIRICHLET ? 2.0 * kf : kind == OR_PERIODIC ? kf : 0.0;
+}
+
 static double vc_diag(const vc_level* L, int i, int j, int k)
 {
     double d = 0.0;
-    d += i > 0 ? VKX(L, i, j, k) : (L->kind[0] == OR_DIRICHLET ? 2.0 * VKX(L, 0, j, k) : 0.0);
-    d += i < L->nx - 1 ? VKX(L, i + 1, j, k) : (L->kind[1] == OR_DIRICHLET ? 2.0 * VKX(L, L->nx, j, k) : 0.0);
-    d += j > 0 ? VKY(L, i, j, k) : (L->kind[2] == OR_DIRICHLET ? 2.0 * VKY(L, i, 0, k) : 0.0);
-    d += j < L->ny - 1 ? VKY(L, i, j + 1, k) : (L->kind[3] == OR_DIRICHLET ? 2.0 * VKY(L, i, L->ny, k) : 0.0);
-    d += k > 0 ? VKZ(L, i, j, k) : (L->kind[4] == OR_DIRICHLET ? 2.0 * VKZ(L, i, j, 0) : 0.0);
-    d += k < L->nz - 1 ? VKZ(L, i, j, k + 1) : (L->kind[5] == OR_DIRICHLET ? 2.0 * VKZ(L, i, j, L->nz) : 0.0);
+    d += i > 0 ? VKX(L, i, j, k) : vc_bdiag(L->kind[0], VKX(L, 0, j, k));
+    d += i < L->nx - 1 ? VKX(L, i + 1, j, k) : vc_bdiag(L->kind[1], VKX(L, L->nx, j, k));
+    d += j > 0 ? VKY(L, i, j, k) : vc_bdiag(L->kind[2], VKY(L, i, 0, k));
+    d += j < L->ny - 1 ? VKY(L, i, j + 1, k) : vc_bdiag(L->kind[3], VKY(L, i, L->ny, k));
+    d += k > 0 ? VKZ(L, i, j, k) : vc_bdiag(L->kind[4], VKZ(L, i, j, 0));
+    d += k < L->nz - 1 ? VKZ(L, i, j, k + 1) : vc_bdiag(L->kind[5], VKZ(L, i, j, L->nz));
     return d;
 }
 
-/* sum over in-domain faces of k_f phi_n, order x-, x+, y-, y+, z-, z+ */
+/* sum over in-domain faces of k_f phi_n (periodic faces reach the cell on the
+ * opposite side), order x-, x+, y-, y+, z-, z+ */
 static double vc_nbsum(const vc_level* L, const double* phi, int i, int j, int k)
 {
-    const size_t nx = L->nx, ny = L->ny;
+    const size_t nx = L->nx, ny = L->ny, nz = L->nz;
     const size_t c = ((size_t)k * ny + j) * nx + i;
     double sum = 0.0;
-    if (i > 0)         sum += VKX(L, i, j, k) * phi[c - 1];
+    if (i > 0) sum += VKX(L, i, j, k) * phi[c - 1];
+    else if (L->kind[0] == OR_PERIODIC) sum += VKX(L, 0, j, k) * phi[c + nx - 1];
     if (i < L->nx - 1) sum += VKX(L, i + 1, j, k) * phi[c + 1];
-    if (j > 0)         sum += VKY(L, i, j, k) * phi[c - nx];
+    else if (L->kind[1] == OR_PERIODIC) sum += VKX(L, L->nx, j, k) * phi[c - (nx - 1)];
+    if (j > 0) sum += VKY(L, i, j, k) * phi[c - nx];
+    else if (L->kind[2] == OR_PERIODIC) sum += VKY(L, i, 0, k) * phi[c + (ny - 1) * nx];
     if (j < L->ny - 1) sum += VKY(L, i, j + 1, k) * phi[c + nx];
-    if (k > 0)         sum += VKZ(L, i, j, k) * phi[c - nx * ny];
+    else if (L->kind[3] == OR_PERIODIC) sum += VKY(L, i, L->ny, k) * phi[c - (ny - 1) * nx];
+    if (k > 0) sum += VKZ(L, i, j, k) * phi[c - nx * ny];
+    else if (L->kind[4] == OR_PERIODIC) sum += VKZ(L, i, j, 0) * phi[c + (nz - 1) * nx * ny];
     if (k < L->nz - 1) sum += VKZ(L, i, j, k + 1) * phi[c + nx * ny];
+    else if (L->kind[5] == OR_PERIODIC) sum += VKZ(L, i, j, L->nz) * phi[c - (nz - 1) * nx * ny];
     return sum;
 }
 
@@ -1058,9 +1103,8 @@ static vc_level vc_make(int nx, int ny, int nz, double h, int level, const int* 
     return L;
 }
 
-void or_vc_faces(int nx, int ny, int nz, const double* eps, double* kx, double* ky, double* kz)
+void or_vc_faces(int nx, int ny, int nz, const int* kinds, const double* eps, double* kx, double* ky, double* kz)
 {
-    const int kinds[6] = {0, 0, 0, 0, 0, 0};
     vc_level L = vc_make(nx, ny, nz, 1.0, 0, kinds, kx, ky, kz);
     vc_faces_from_eps(&L, eps);
 }
@@ -1111,7 +1155,8 @@ void or_vc_fold(int nx, int ny, int nz, double h, const int* kinds, const double
                 if (ax == 0)      { i = hi ? nx - 1 : 0; j = u; k = v; kf = VKX(&L, hi ? nx : 0, j, k); }
                 else if (ax == 1) { j = hi ? ny - 1 : 0; i = u; k = v; kf = VKY(&L, i, hi ? ny : 0, k); }
                 else              { k = hi ? nz - 1 : 0; i = u; j = v; kf = VKZ(&L, i, j, hi ? nz : 0); }
-                const double t = kinds[fc] == OR_DIRICHLET ? 2.0 * kf * g / (h * h) : kf * g / h;
+                const double t = kinds[fc] == OR_DIRICHLET ? 2.0 * kf * g / (h * h)
+                                 : kinds[fc] == OR_NEUMANN ? kf * g / h : 0.0;
                 b[((size_t)k * ny + j) * nx + i] += t;
             }
     }

@@ -152,3 +152,79 @@ def test_jumping_permittivity_converges(orc):
         rates.append((hist[-1] / hist[1]) ** (1.0 / (len(hist) - 2)))
     assert max(rates) < 0.3, rates
     assert rates[1] < 1.5 * rates[0] + 0.02, rates
+
+
+# ---- periodic faces (Sec. 2.4: they cyclically extend the domain) -------------
+P = 2   # periodic face kind
+PERIODIC_KINDS = [(P, P, P, P, D, D), (P, P, N, D, P, P), (D, N, P, P, N, D)]
+
+
+@pytest.mark.parametrize("kinds", PERIODIC_KINDS[:1])
+def test_periodic_eigenmodes(orc, kinds):
+    """cos(2 pi m (i+1/2)/nx) cos(2 pi m'(j+1/2)/ny) sin(pi p (k+1/2)/nz) is an
+    eigenvector with eigenvalue s (2-2cos(2 pi m/nx) + 2-2cos(2 pi m'/ny) + 2-2cos(pi p/nz))."""
+    nx, ny, nz, h = 8, 6, 10, 0.4
+    k = orc.vc_faces(np.ones((nz, ny, nx)), kinds)
+    i, j, kk = np.arange(nx) + 0.5, np.arange(ny) + 0.5, np.arange(nz) + 0.5
+    for m, m2, p in ((1, 2, 1), (3, 1, 4), (4, 3, 7)):
+        v = (np.sin(np.pi * p * kk / nz)[:, None, None] * np.cos(2 * np.pi * m2 * j / ny)[None, :, None] *
+             np.cos(2 * np.pi * m * i / nx)[None, None, :])
+        lam = (2 - 2 * np.cos(2 * np.pi * m / nx) + 2 - 2 * np.cos(2 * np.pi * m2 / ny) +
+               2 - 2 * np.cos(np.pi * p / nz)) / (h * h)
+        assert np.allclose(orc.vc_apply(v, h, kinds, k), lam * v, rtol=0, atol=1e-12 * lam)
+
+
+@pytest.mark.parametrize("kinds", PERIODIC_KINDS)
+def test_periodic_galerkin_and_definiteness(orc, kinds):
+    fine, h = (4, 6, 4), 0.5
+    eps = random_eps(fine, 17)
+    k0 = orc.vc_faces(eps, kinds)
+    A0 = vc_dense(orc, fine, h, kinds, k0, 0)
+    A1 = vc_dense(orc, (2, 3, 2), h, kinds, orc.vc_coarsen(k0), 1)
+    Pm = prolongation_matrix(fine)
+    assert np.allclose(Pm.T @ A0 @ Pm / 8.0, A1, rtol=1e-13, atol=1e-12 * np.abs(A1).max())
+    assert np.abs(A0 - A0.T).max() <= 1e-13 * np.abs(A0).max()
+    assert np.linalg.eigvalsh(A0).min() > 0.0
+
+
+def test_periodic_translation_invariance(orc):
+    """Shifting eps and f cyclically along periodic x and y shifts the solution."""
+    kinds, values = (P, P, P, P, D, D), (0, 0, 0, 0, 0.5, -0.3)
+    shape, h = (16, 8, 16), 1.0 / 16
+    eps, f = random_eps(shape, 31, 0.5, 5.0), W.random_field(shape, 32)
+    def solve(e, ff):
+        b = orc.vc_fold(ff, h, kinds, values, orc.vc_faces(e, kinds))
+        phi, _, st = orc.vc_solve(b, h, kinds, 3, e, rtol=1e-13)
+        assert st == 0
+        return phi
+    base = solve(eps, f)
+    sh = solve(np.roll(eps, (3, 5), axis=(1, 2)), np.roll(f, (3, 5), axis=(1, 2)))
+    assert np.abs(sh - np.roll(base, (3, 5), axis=(1, 2))).max() <= 1e-10 * np.abs(base).max()
+
+
+@pytest.mark.parametrize("kinds", PERIODIC_KINDS)
+def test_periodic_multigrid_matches_dense_solve(orc, kinds):
+    shape, h = (8, 8, 8), 1.0 / 8
+    eps = random_eps(shape, 41, 0.2, 20.0)
+    k = orc.vc_faces(eps, kinds)
+    b = orc.vc_fold(W.random_field(shape, 42), h, kinds, (0.3, -0.2, 0.1, 0.0, 1.0, -1.0), k)
+    ref = np.linalg.solve(vc_dense(orc, shape, h, kinds, k), b.ravel()).reshape(b.shape)
+    phi, _, st = orc.vc_solve(b, h, kinds, 3, eps, rtol=1e-13)
+    assert st == 0 and np.abs(phi - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_periodic_gradient_of_a_sine(orc):
+    """phi = sin(2 pi x / L) on a periodic x axis: every D3Q19 pair with an x
+    step carries the same central difference, so grad_x = cos(x') sin(h')/h
+    (x' = 2 pi x / L, h' = 2 pi h / L) exactly, on the wrapped cells too."""
+    nx, ny, nz, L = 16, 6, 8, 2.0
+    h = L / nx
+    kinds = (P, P, N, N, D, D)
+    x = (np.arange(nx) + 0.5) * h
+    phi = np.broadcast_to(np.sin(2 * np.pi * x / L), (nz, ny, nx)).copy()
+    g = orc.gradient(phi, h, kinds, (0.0,) * 6)
+    want = np.cos(2 * np.pi * x / L) * np.sin(2 * np.pi * h / L) / h
+    inner = (slice(1, -1), slice(1, -1), slice(None))   # away from the non-periodic y/z layers
+    assert np.allclose(g[0][inner], np.broadcast_to(want, (nz, ny, nx))[inner], rtol=0, atol=1e-13)
+    # the boundary layers of y/z use D3Q7 in x, also exact: (phi(x+h) - phi(x-h)) / 2h
+    assert np.allclose(g[0][0], np.broadcast_to(want, (ny, nx)), rtol=0, atol=1e-13)
