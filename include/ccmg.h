@@ -40,8 +40,15 @@ extern "C" {
 
 typedef struct ccmg_solver ccmg_solver;
 
-/* face kinds; faces are numbered 0..5 = x-, x+, y-, y+, z-, z+ */
-enum { CCMG_DIRICHLET = 0, CCMG_NEUMANN = 1 };
+/* face kinds; faces are numbered 0..5 = x-, x+, y-, y+, z-, z+.
+ * CCMG_PERIODIC (Sec. 2.4: the domain is cyclically extended; the cells at
+ * opposite sides are neighbours) must be set on both faces of an axis; its
+ * value is ignored.  A solver with a periodic axis runs on the stored-stencil
+ * operator of ccmg_set_permittivity (unit permittivity until one is set; its
+ * workspace includes the face coefficients) and in FP64 only.  Spheres of the
+ * deposition and force calls are clipped at every face, periodic ones
+ * included: keep them clear of periodic boundaries. */
+enum { CCMG_DIRICHLET = 0, CCMG_NEUMANN = 1, CCMG_PERIODIC = 2 };
 
 /* precision modes */
 enum { CCMG_FP64 = 0, CCMG_FP32_IR = 1 };

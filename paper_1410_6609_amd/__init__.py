@@ -20,11 +20,11 @@ from typing import Optional, Sequence, Tuple
 import torch
 
 __all__ = [
-    "DIRICHLET", "NEUMANN", "FP64", "FP32_IR", "SPREAD", "VOLUME", "CcmgError", "Options", "Stats", "Solver",
+    "DIRICHLET", "NEUMANN", "PERIODIC", "FP64", "FP32_IR", "SPREAD", "VOLUME", "CcmgError", "Options", "Stats", "Solver",
     "PoissonFn", "RhsSolveFn", "lib", "LIB_PATH", "exported_symbols",
 ]
 
-DIRICHLET, NEUMANN = 0, 1
+DIRICHLET, NEUMANN, PERIODIC = 0, 1, 2
 FP64, FP32_IR = 0, 1
 SPREAD, VOLUME = 0, 1   # normalisations of the sub-sampled deposition
 MAX_SUBSAMPLE = 8

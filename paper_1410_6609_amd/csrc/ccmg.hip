@@ -103,6 +103,7 @@ struct ccmg_solver {
     double h;
     ccmg_face bc[6];
     int sh[6];
+    bool periodic = false;       // some axis is periodic
     ccmg_options opt;
     hipStream_t stream = nullptr;
     int L = 0;
@@ -541,6 +542,7 @@ VcLevel vc_level(const ccmg_solver* s, int l)
     V.ny = s->lv[l].ny;
     V.nz = s->lv[l].nz;
     for (int fc = 0; fc < 6; ++fc) V.dir[fc] = s->bc[fc].kind == CCMG_DIRICHLET;
+    for (int a = 0; a < 3; ++a) V.per[a] = s->bc[2 * a].kind == CCMG_PERIODIC;
     return V;
 }
 
@@ -944,6 +946,7 @@ GradBc grad_bc(const ccmg_solver* s)
         B.value[fc] = s->bc[fc].value;
         B.face[fc] = s->face_on[fc] ? s->face_vals[fc] : nullptr;
     }
+    for (int a = 0; a < 3; ++a) B.per[a] = s->bc[2 * a].kind == CCMG_PERIODIC;
     return B;
 }
 
@@ -1008,11 +1011,22 @@ int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_
     if (o.variable_eps != 0 && o.variable_eps != 1) return fail(nullptr, CCMG_E_ARG, "variable_eps must be 0 or 1");
     if (o.variable_eps && o.precision != CCMG_FP64)
         return fail(nullptr, CCMG_E_ARG, "variable permittivity is solved in FP64 only");
-    bool any_dirichlet = false;
+    bool any_dirichlet = false, any_periodic = false;
     for (int f = 0; f < 6; ++f) {
-        if (bc[f].kind != CCMG_DIRICHLET && bc[f].kind != CCMG_NEUMANN) return fail(nullptr, CCMG_E_ARG, "bad face kind");
+        if (bc[f].kind != CCMG_DIRICHLET && bc[f].kind != CCMG_NEUMANN && bc[f].kind != CCMG_PERIODIC)
+            return fail(nullptr, CCMG_E_ARG, "bad face kind");
         if (!std::isfinite(bc[f].value)) return fail(nullptr, CCMG_E_ARG, "face value not finite");
         any_dirichlet |= bc[f].kind == CCMG_DIRICHLET;
+        any_periodic |= bc[f].kind == CCMG_PERIODIC;
+    }
+    for (int a = 0; a < 3; ++a)
+        if ((bc[2 * a].kind == CCMG_PERIODIC) != (bc[2 * a + 1].kind == CCMG_PERIODIC))
+            return fail(nullptr, CCMG_E_ARG, "periodic faces come in pairs (axis %d)", a);
+    if (any_periodic) {
+        // periodic faces run on the stored-stencil operator (unit permittivity
+        // unless one is set)
+        if (o.precision != CCMG_FP64) return fail(nullptr, CCMG_E_ARG, "periodic faces are solved in FP64 only");
+        o.variable_eps = 1;
     }
     if (!any_dirichlet) return fail(nullptr, CCMG_E_SINGULAR, "all faces Neumann: the operator is singular");
     // hierarchy depth
@@ -1043,6 +1057,7 @@ int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_
         s->sh[f] = bc[f].kind == CCMG_DIRICHLET ? 1 : -1;
     }
     s->opt = o;
+    s->periodic = any_periodic;
     s->opt.levels = L;
     s->stream = (hipStream_t)hip_stream;
     s->L = L;
@@ -1067,6 +1082,10 @@ int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_
 
 size_t ccmg_workspace_bytes(const ccmg_solver* s) { return s ? s->need_bytes : 0; }
 
+namespace {
+int vc_unit_faces(ccmg_solver* s);
+}  // namespace
+
 int ccmg_set_workspace(ccmg_solver* s, void* d_ptr, size_t bytes)
 {
     if (!s) return CCMG_E_ARG;
@@ -1085,6 +1104,7 @@ int ccmg_set_workspace(ccmg_solver* s, void* d_ptr, size_t bytes)
     if (layout_workspace(s, base) != s->need_bytes) return fail(s, CCMG_E_STATE, "internal: workspace layout mismatch");
     s->ws = base;
     s->ws_bytes = bytes;
+    if (s->periodic) return vc_unit_faces(s);
     return CCMG_OK;
 }
 
@@ -1214,6 +1234,24 @@ int ccmg_coulomb_adjoint(ccmg_solver* s, const double* d_phi, int n, const doubl
     return CCMG_OK;
 }
 
+namespace {
+// unit permittivity on every level (the periodic solver's default operator)
+int vc_unit_faces(ccmg_solver* s)
+{
+    for (int l = 0; l < s->L; ++l) {
+        const LevelBuf& B = s->lv[l];
+        const size_t nfx = (size_t)(B.nx + 1) * B.ny * B.nz, nfy = (size_t)B.nx * (B.ny + 1) * B.nz,
+                     nfz = (size_t)B.nx * B.ny * (B.nz + 1);
+        hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(nfx)), dim3(256), 0, s->stream, s->vkx[l], nfx, 1.0);
+        hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(nfy)), dim3(256), 0, s->stream, s->vky[l], nfy, 1.0);
+        hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(nfz)), dim3(256), 0, s->stream, s->vkz[l], nfz, 1.0);
+    }
+    LAUNCHCHK(s);
+    s->vc_on = true;
+    return CCMG_OK;
+}
+}  // namespace
+
 int ccmg_set_permittivity(ccmg_solver* s, const double* d_eps)
 {
     int rc = check_ready(s);
@@ -1221,6 +1259,7 @@ int ccmg_set_permittivity(ccmg_solver* s, const double* d_eps)
     s->err.clear();
     if (!s->opt.variable_eps) return fail(s, CCMG_E_STATE, "solver created without variable_eps");
     if (d_eps == nullptr) {
+        if (s->periodic) return vc_unit_faces(s);
         s->vc_on = false;
         return CCMG_OK;
     }
@@ -1228,8 +1267,9 @@ int ccmg_set_permittivity(ccmg_solver* s, const double* d_eps)
     const LevelBuf& B = s->lv[0];
     const size_t nf = (size_t)(B.nx + 1) * B.ny * B.nz + (size_t)B.nx * (B.ny + 1) * B.nz +
                       (size_t)B.nx * B.ny * (B.nz + 1);
+    const VcLevel V0 = vc_level(s, 0);
     hipLaunchKernelGGL(k_vc_faces, dim3(vc_grid(nf)), dim3(256), 0, s->stream, d_eps, s->vkx[0], s->vky[0], s->vkz[0],
-                       B.nx, B.ny, B.nz);
+                       B.nx, B.ny, B.nz, V0.per[0], V0.per[1], V0.per[2]);
     for (int l = 0; l + 1 < s->L; ++l) {
         const LevelBuf& C = s->lv[l + 1];
         const size_t nc = (size_t)(C.nx + 1) * C.ny * C.nz + (size_t)C.nx * (C.ny + 1) * C.nz +

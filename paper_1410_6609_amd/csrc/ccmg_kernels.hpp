@@ -1380,13 +1380,23 @@ struct GradBc {
     int dirichlet[6];
     double value[6];
     const double* face[6];   // per-cell boundary values, or null
+    int per[3];              // periodic axes
 };
+
+// indices on periodic axes taken modulo the extent
+__device__ __forceinline__ void wrap3(const int* per, int nx, int ny, int nz, int& i, int& j, int& k)
+{
+    if (per[0]) i = i < 0 ? i + nx : (i >= nx ? i - nx : i);
+    if (per[1]) j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
+    if (per[2]) k = k < 0 ? k + nz : (k >= nz ? k - nz : k);
+}
 
 // phi at (i,j,k), or the ghost value one layer outside across one face:
 // Dirichlet 2 g - phi_b, Neumann phi_b + h g_n (g_n the outward derivative)
 __device__ __forceinline__ double phi_or_ghost(const double* phi, const GradBc& B, int i, int j, int k)
 {
 #pragma clang fp contract(off)
+    wrap3(B.per, B.nx, B.ny, B.nz, i, j, k);
     int fc = -1, ii = i, jj = j, kk = k;
     if (i < 0) { fc = 0; ii = 0; }
     else if (i >= B.nx) { fc = 1; ii = B.nx - 1; }
@@ -1412,7 +1422,25 @@ __device__ __forceinline__ void grad_at(const double* phi, const GradBc& B, int 
 {
 #pragma clang fp contract(off)
     const size_t sy = (size_t)B.nx, sz = (size_t)B.nx * B.ny;
-    if (i > 0 && i < B.nx - 1 && j > 0 && j < B.ny - 1 && k > 0 && k < B.nz - 1) {
+    const bool in_x = i > 0 && i < B.nx - 1, in_y = j > 0 && j < B.ny - 1, in_z = k > 0 && k < B.nz - 1;
+    if ((in_x || B.per[0]) && (in_y || B.per[1]) && (in_z || B.per[2]) && !(in_x && in_y && in_z)) {
+        // D3Q19 across a periodic boundary: neighbours by wrapped index
+        auto P = [&](int dx, int dy, int dz) {
+            int a = i + dx, b = j + dy, c = k + dz;
+            wrap3(B.per, B.nx, B.ny, B.nz, a, b, c);
+            return phi[(size_t)c * sz + (size_t)b * sy + a];
+        };
+        const double ax = P(1, 0, 0) - P(-1, 0, 0), ay = P(0, 1, 0) - P(0, -1, 0), az = P(0, 0, 1) - P(0, 0, -1);
+        const double xya = P(1, 1, 0) - P(-1, -1, 0), xyb = P(1, -1, 0) - P(-1, 1, 0);
+        const double xza = P(1, 0, 1) - P(-1, 0, -1), xzb = P(1, 0, -1) - P(-1, 0, 1);
+        const double yza = P(0, 1, 1) - P(0, -1, -1), yzb = P(0, 1, -1) - P(0, -1, 1);
+        const double s = 3.0 / B.h;
+        gx = s * (ax * (1.0 / 18.0) + ((xya + xyb) + (xza + xzb)) * (1.0 / 36.0));
+        gy = s * (ay * (1.0 / 18.0) + ((xya - xyb) + (yza + yzb)) * (1.0 / 36.0));
+        gz = s * (az * (1.0 / 18.0) + ((xza - xzb) + (yza - yzb)) * (1.0 / 36.0));
+        return;
+    }
+    if (in_x && in_y && in_z) {
         const double* p = phi + (k * sz + j * sy + i);
         const double ax = p[1] - p[-1];
         const double ay = p[sy] - p[-(ptrdiff_t)sy];
@@ -1507,7 +1535,23 @@ __device__ __forceinline__ void scatter_grad_t(const GradBc& B, int i, int j, in
 {
     const size_t sy = (size_t)B.nx, sz = (size_t)B.nx * B.ny;
     const size_t c = (size_t)k * sz + (size_t)j * sy + i;
-    if (i > 0 && i < B.nx - 1 && j > 0 && j < B.ny - 1 && k > 0 && k < B.nz - 1) {
+    const bool in_x = i > 0 && i < B.nx - 1, in_y = j > 0 && j < B.ny - 1, in_z = k > 0 && k < B.nz - 1;
+    if ((in_x || B.per[0]) && (in_y || B.per[1]) && (in_z || B.per[2]) && !(in_x && in_y && in_z)) {
+        auto A = [&](int dx, int dy, int dz, double v) {
+            int a = i + dx, b = j + dy, cc = k + dz;
+            wrap3(B.per, B.nx, B.ny, B.nz, a, b, cc);
+            atomicAdd(&mu[(size_t)cc * sz + (size_t)b * sy + a], v);
+        };
+        const double s = 3.0 / B.h;
+        const double ax = s * vx * (1.0 / 18.0), ay = s * vy * (1.0 / 18.0), az = s * vz * (1.0 / 18.0);
+        const double d = s * (1.0 / 36.0);
+        A(1, 0, 0, ax); A(-1, 0, 0, -ax); A(0, 1, 0, ay); A(0, -1, 0, -ay); A(0, 0, 1, az); A(0, 0, -1, -az);
+        A(1, 1, 0, d * (vx + vy)); A(-1, -1, 0, -d * (vx + vy)); A(1, -1, 0, d * (vx - vy)); A(-1, 1, 0, -d * (vx - vy));
+        A(1, 0, 1, d * (vx + vz)); A(-1, 0, -1, -d * (vx + vz)); A(1, 0, -1, d * (vx - vz)); A(-1, 0, 1, -d * (vx - vz));
+        A(0, 1, 1, d * (vy + vz)); A(0, -1, -1, -d * (vy + vz)); A(0, 1, -1, d * (vy - vz)); A(0, -1, 1, -d * (vy - vz));
+        return;
+    }
+    if (in_x && in_y && in_z) {
         const double s = 3.0 / B.h;
         const double ax = s * vx * (1.0 / 18.0), ay = s * vy * (1.0 / 18.0), az = s * vz * (1.0 / 18.0);
         atomicAdd(&mu[c + 1], ax);
@@ -1539,9 +1583,12 @@ __device__ __forceinline__ void scatter_grad_t(const GradBc& B, int i, int j, in
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double cf = v[a] * inv2h;
+        const size_t wrapv = (size_t)(n[a] - 1) * st[a];   // periodic: across to the opposite side
         if (pos[a] + 1 < n[a]) atomicAdd(&mu[c + st[a]], cf);
+        else if (B.per[a]) atomicAdd(&mu[c - wrapv], cf);
         else atomicAdd(&mu[c], B.dirichlet[2 * a + 1] ? -cf : cf);
         if (pos[a] - 1 >= 0) atomicAdd(&mu[c - st[a]], -cf);
+        else if (B.per[a]) atomicAdd(&mu[c + wrapv], -cf);
         else atomicAdd(&mu[c], B.dirichlet[2 * a] ? cf : -cf);
     }
 }
@@ -1613,6 +1660,7 @@ struct VcLevel {
     const double* kz;
     int nx, ny, nz;
     int dir[6];   // 1: Dirichlet face
+    int per[3];   // periodic axes: the boundary face couples cell n-1 and cell 0
 };
 
 __device__ __forceinline__ size_t vc_ix(const VcLevel& L, int i, int j, int k)
@@ -1637,13 +1685,20 @@ __device__ __forceinline__ void vc_row(const VcLevel& L, const double* phi, int 
     const double kxm = L.kx[vc_ix(L, i, j, k)], kxp = L.kx[vc_ix(L, i + 1, j, k)];
     const double kym = L.ky[vc_iy(L, i, j, k)], kyp = L.ky[vc_iy(L, i, j + 1, k)];
     const double kzm = L.kz[vc_iz(L, i, j, k)], kzp = L.kz[vc_iz(L, i, j, k + 1)];
+    const size_t wx = (size_t)(L.nx - 1), wy = (size_t)(L.ny - 1) * sy, wz = (size_t)(L.nz - 1) * sz;
     double dd = 0.0, ss = 0.0;
-    if (i > 0) { dd += kxm; ss += kxm * phi[c - 1]; } else if (L.dir[0]) dd += 2.0 * kxm;
-    if (i < L.nx - 1) { dd += kxp; ss += kxp * phi[c + 1]; } else if (L.dir[1]) dd += 2.0 * kxp;
-    if (j > 0) { dd += kym; ss += kym * phi[c - sy]; } else if (L.dir[2]) dd += 2.0 * kym;
-    if (j < L.ny - 1) { dd += kyp; ss += kyp * phi[c + sy]; } else if (L.dir[3]) dd += 2.0 * kyp;
-    if (k > 0) { dd += kzm; ss += kzm * phi[c - sz]; } else if (L.dir[4]) dd += 2.0 * kzm;
-    if (k < L.nz - 1) { dd += kzp; ss += kzp * phi[c + sz]; } else if (L.dir[5]) dd += 2.0 * kzp;
+    if (i > 0) { dd += kxm; ss += kxm * phi[c - 1]; }
+    else if (L.per[0]) { dd += kxm; ss += kxm * phi[c + wx]; } else if (L.dir[0]) dd += 2.0 * kxm;
+    if (i < L.nx - 1) { dd += kxp; ss += kxp * phi[c + 1]; }
+    else if (L.per[0]) { dd += kxp; ss += kxp * phi[c - wx]; } else if (L.dir[1]) dd += 2.0 * kxp;
+    if (j > 0) { dd += kym; ss += kym * phi[c - sy]; }
+    else if (L.per[1]) { dd += kym; ss += kym * phi[c + wy]; } else if (L.dir[2]) dd += 2.0 * kym;
+    if (j < L.ny - 1) { dd += kyp; ss += kyp * phi[c + sy]; }
+    else if (L.per[1]) { dd += kyp; ss += kyp * phi[c - wy]; } else if (L.dir[3]) dd += 2.0 * kyp;
+    if (k > 0) { dd += kzm; ss += kzm * phi[c - sz]; }
+    else if (L.per[2]) { dd += kzm; ss += kzm * phi[c + wz]; } else if (L.dir[4]) dd += 2.0 * kzm;
+    if (k < L.nz - 1) { dd += kzp; ss += kzp * phi[c + sz]; }
+    else if (L.per[2]) { dd += kzp; ss += kzp * phi[c - wz]; } else if (L.dir[5]) dd += 2.0 * kzp;
     d = dd;
     sum = ss;
 }
@@ -1652,7 +1707,8 @@ __device__ __forceinline__ double harmonic_mean(double a, double b) { return 2.0
 
 // finest-level face coefficients from the cell permittivity: one thread per
 // face of each orientation (boundary faces take their cell's value)
-__global__ void k_vc_faces(const double* eps, double* kx, double* ky, double* kz, int nx, int ny, int nz)
+__global__ void k_vc_faces(const double* eps, double* kx, double* ky, double* kz, int nx, int ny, int nz, int px,
+                           int py, int pz)
 {
     const size_t nfx = (size_t)(nx + 1) * ny * nz, nfy = (size_t)nx * (ny + 1) * nz, nfz = (size_t)nx * ny * (nz + 1);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -1660,15 +1716,18 @@ __global__ void k_vc_faces(const double* eps, double* kx, double* ky, double* kz
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nfx + nfy + nfz; t += stride) {
         if (t < nfx) {
             const int i = (int)(t % (nx + 1)), j = (int)((t / (nx + 1)) % ny), k = (int)(t / ((size_t)(nx + 1) * ny));
-            kx[t] = i == 0 ? E(0, j, k) : i == nx ? E(nx - 1, j, k) : harmonic_mean(E(i - 1, j, k), E(i, j, k));
+            kx[t] = (i == 0 || i == nx) ? (px ? harmonic_mean(E(nx - 1, j, k), E(0, j, k)) : E(i == 0 ? 0 : nx - 1, j, k))
+                                        : harmonic_mean(E(i - 1, j, k), E(i, j, k));
         } else if (t < nfx + nfy) {
             const size_t u = t - nfx;
             const int i = (int)(u % nx), j = (int)((u / nx) % (ny + 1)), k = (int)(u / ((size_t)nx * (ny + 1)));
-            ky[u] = j == 0 ? E(i, 0, k) : j == ny ? E(i, ny - 1, k) : harmonic_mean(E(i, j - 1, k), E(i, j, k));
+            ky[u] = (j == 0 || j == ny) ? (py ? harmonic_mean(E(i, ny - 1, k), E(i, 0, k)) : E(i, j == 0 ? 0 : ny - 1, k))
+                                        : harmonic_mean(E(i, j - 1, k), E(i, j, k));
         } else {
             const size_t u = t - nfx - nfy;
             const int i = (int)(u % nx), j = (int)((u / nx) % ny), k = (int)(u / ((size_t)nx * ny));
-            kz[u] = k == 0 ? E(i, j, 0) : k == nz ? E(i, j, nz - 1) : harmonic_mean(E(i, j, k - 1), E(i, j, k));
+            kz[u] = (k == 0 || k == nz) ? (pz ? harmonic_mean(E(i, j, nz - 1), E(i, j, 0)) : E(i, j, k == 0 ? 0 : nz - 1))
+                                        : harmonic_mean(E(i, j, k - 1), E(i, j, k));
         }
     }
 }
@@ -1712,7 +1771,7 @@ struct VcFold {
 
 __device__ __forceinline__ double vc_bterm(const VcFold& P, const VcLevel& L, int fc, size_t at, double kf)
 {
-    if (P.homogeneous) return 0.0;
+    if (P.homogeneous || L.per[fc / 2]) return 0.0;
     const double g = P.face[fc] != nullptr ? P.face[fc][at] : P.value[fc];
     return L.dir[fc] ? 2.0 * kf * g / (P.h * P.h) : kf * g / P.h;
 }

@@ -103,6 +103,24 @@ def test_calls_without_workspace_fail_cleanly():
     L.ccmg_destroy(hd)
 
 
+@pytest.mark.parametrize("kinds,opt,code", [
+    ((2, 0, 1, 1, 0, 0), {}, pkg.E_ARG),                        # periodic faces must pair
+    ((2, 2, 2, 2, 1, 1), {}, pkg.E_SINGULAR),                   # no Dirichlet face
+    ((2, 2, 1, 1, 0, 0), dict(precision=pkg.FP32_IR), pkg.E_ARG),
+    ((2, 2, 1, 1, 0, 0), {}, pkg.OK),
+    ((3, 3, 1, 1, 0, 0), {}, pkg.E_ARG),
+])
+def test_periodic_face_validation(kinds, opt, code):
+    rc, hd = create((32, 32, 32), kinds, **opt)
+    assert rc == code
+    if rc == 0:
+        # the stored-stencil workspace is reserved without asking for variable_eps
+        rc0, h0 = create((32, 32, 32), ZD)
+        assert pkg.lib().ccmg_workspace_bytes(hd) > pkg.lib().ccmg_workspace_bytes(h0)
+        pkg.lib().ccmg_destroy(h0)
+        pkg.lib().ccmg_destroy(hd)
+
+
 def test_variable_permittivity_options():
     rc, _ = create((32, 32, 32), ZD, variable_eps=2)
     assert rc == pkg.E_ARG

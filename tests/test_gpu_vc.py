@@ -150,3 +150,69 @@ def test_vc_full_size_spheres_256():
     b = oracle.vc_fold(f.cpu().numpy(), w.h, w.kinds, w.values, k)
     r = b - oracle.vc_apply(phi.cpu().numpy(), w.h, w.kinds, k)
     assert np.linalg.norm(r) / np.linalg.norm(b) < 1.0001e-10
+
+
+# ---- periodic faces -----------------------------------------------------------------
+P = pkg.PERIODIC
+PER_CASES = [((64, 48, 40), 3, (P, P, P, P, D, D), (0, 0, 0, 0, 0.2, -0.4)),
+             ((96, 80, 72), 4, (P, P, N, D, P, P), (0, 0, 0.3, 1.0, 0, 0)),
+             ((32, 64, 48), 3, (D, N, P, P, N, D), (0.5, -0.1, 0, 0, 0.2, 0.0))]
+
+
+@pytest.mark.parametrize("unit", [True, False])
+@pytest.mark.parametrize("case", PER_CASES, ids=ids)
+def test_periodic_solve_parity(case, unit):
+    shape, levels, kinds, values = case
+    log_case("periodic", shape, unit)
+    h = 1.0 / shape[0]
+    nx, ny, nz = shape
+    eps = np.ones((nz, ny, nx)) if unit else lognormal_eps(shape, 13)
+    s = pkg.Solver(shape, h, list(zip(kinds, values)), pkg.Options(levels=levels), device=DEV)
+    if not unit:
+        s.set_permittivity(to_dev(eps))
+    f = rhs(shape, 14)
+    fd = to_dev(f)
+    b = oracle.vc_fold(f, h, kinds, values, oracle.vc_faces(eps, kinds))
+    phi = s.zeros()
+    ref = np.zeros_like(f)
+    for k in range(1, 3):
+        rel = s.vcycle(phi, fd)
+        ref, hist, _ = oracle.vc_solve(b, h, kinds, levels, eps, rtol=0.0, max_cycles=1, phi0=ref)
+        assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max(), k
+        assert abs(rel - hist[-1]) <= 1e-9 * hist[-1]
+    phi, st = s.solve(fd, rtol=1e-10)
+    ref, hist, ost = oracle.vc_solve(b, h, kinds, levels, eps, rtol=1e-10)
+    assert ost == 0 and st.cycles == len(hist) - 1
+    assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    if not unit:   # back to unit permittivity (a periodic solver stays on stored stencils)
+        s.set_permittivity(None)
+        phi1, _ = s.solve(fd, rtol=1e-10)
+        b1 = oracle.vc_fold(f, h, kinds, values, oracle.vc_faces(np.ones_like(eps), kinds))
+        ref1, _, _ = oracle.vc_solve(b1, h, kinds, levels, np.ones_like(eps), rtol=1e-10)
+        assert np.abs(phi1.cpu().numpy() - ref1).max() <= 1e-12 * np.abs(ref1).max()
+
+
+@pytest.mark.parametrize("case", PER_CASES, ids=ids)
+def test_periodic_gradient_force_and_adjoint(case):
+    shape, levels, kinds, values = case
+    log_case("periodic gradient", shape)
+    h = 1.0
+    s = pkg.Solver(shape, h, list(zip(kinds, values)), pkg.Options(levels=levels), device=DEV)
+    phi = rhs(shape, 15)
+    g = s.gradient(to_dev(phi)).cpu().numpy()
+    ref = oracle.gradient(phi, h, kinds, values)
+    assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+    nx, ny, nz = shape
+    rng = np.random.default_rng(16)
+    n = 12
+    r = rng.uniform(2.0, 4.0, n)
+    c = np.column_stack([rng.uniform(r, nx - r), rng.uniform(r, ny - r), rng.uniform(r, nz - r)])
+    q = rng.choice([-1.0, 1.0], n)
+    gF = rng.standard_normal((n, 3))
+    F = s.coulomb_force(to_dev(phi), to_dev(c), to_dev(r), to_dev(q), 2, pkg.VOLUME).cpu().numpy()
+    Fr = oracle.coulomb(phi, h, kinds, values, c, r, q, 2, pkg.VOLUME)
+    assert np.abs(F - Fr).max() <= 1e-12 * np.abs(Fr).max()
+    mu, d = s.coulomb_adjoint(to_dev(phi), to_dev(c), to_dev(r), to_dev(q), to_dev(gF), 2, pkg.VOLUME)
+    mur, dr = oracle.coulomb_adjoint(phi, h, kinds, values, c, r, q, gF, 2, pkg.VOLUME)
+    assert np.abs(mu.cpu().numpy() - mur).max() <= 1e-12 * np.abs(mur).max()
+    assert np.abs(d.cpu().numpy() - dr).max() <= 1e-12 * np.abs(dr).max()
