@@ -38,8 +38,16 @@ namespace {
 #ifndef CCMG_WAVES
 #define CCMG_WAVES 8
 #endif
+// FP32 passes hold half the registers and LDS per strip: 16-wave blocks
+// (64-row tiles, less halo) fit; FP64 passes keep 8 waves
+#ifndef CCMG_WAVES_F32
+#define CCMG_WAVES_F32 16
+#endif
 constexpr int kM = CCMG_ROWS;
 constexpr int kWY = CCMG_WAVES;
+// waves (strip pairs) per block of the smoother passes, per storage type
+template <typename T>
+constexpr int kWYof = sizeof(T) == 4 ? CCMG_WAVES_F32 : CCMG_WAVES;
 
 struct LevelBuf {
     int nx = 0, ny = 0, nz = 0;
@@ -93,7 +101,8 @@ Grid pass_grid(int nx, int ny, int nz, int tx, int ty, int S, int capacity)
 constexpr int kMaxHalo = 6;
 int max_pass_blocks(int nx, int ny, int nz)
 {
-    return cdiv(nx, 64 - 2 * kMaxHalo) * cdiv(ny, 2 * CCMG_WAVES * CCMG_ROWS - 2 * kMaxHalo) * cdiv(nz, 2);
+    const int wy = CCMG_WAVES < CCMG_WAVES_F32 ? CCMG_WAVES : CCMG_WAVES_F32;
+    return cdiv(nx, 64 - 2 * kMaxHalo) * cdiv(ny, 2 * wy * CCMG_ROWS - 2 * kMaxHalo) * cdiv(nz, 2);
 }
 
 }  // namespace
@@ -188,12 +197,13 @@ constexpr size_t kBottomMaxLds = 160 * 1024;
 template <typename T, int SPHI, int LOAD, int RES>
 bool launch_one(const PassParams<T>& P0, hipStream_t st)
 {
-    using Sh = PassShape<T, SPHI, RES, kM, kWY, LOAD>;
-    auto kern = k_pass<T, SPHI, LOAD, RES, kM, kWY>;
+    constexpr int WYT = kWYof<T>;
+    using Sh = PassShape<T, SPHI, RES, kM, WYT, LOAD>;
+    auto kern = k_pass<T, SPHI, LOAD, RES, kM, WYT>;
     static int per_cu = 0;
     if (per_cu == 0) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kern), 64 * kWY, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kern), 64 * WYT, 0) !=
                 hipSuccess || nb < 1) {
             (void)hipGetLastError();
             nb = 1;
@@ -209,7 +219,7 @@ bool launch_one(const PassParams<T>& P0, hipStream_t st)
     P.zc = g.zc;
     // the norm reduction stores one partial per block
     if ((RES == RES_NORM || RES == RES_NORM_R32 || RES == RES_STORE) && g.blocks() > P.max_partials) return false;
-    hipLaunchKernelGGL(kern, dim3(g.blocks()), dim3(64 * kWY), 0, st, P);
+    hipLaunchKernelGGL(kern, dim3(g.blocks()), dim3(64 * WYT), 0, st, P);
     return true;
 }
 
