@@ -228,6 +228,8 @@ def main():
     ap.add_argument("--inner", type=int, default=2)
     ap.add_argument("--no-scene", action="store_true", help="skip the time-step scene")
     ap.add_argument("--no-vc", action="store_true", help="skip the variable-permittivity solve")
+    ap.add_argument("--only", choices=("scene", "vc"), default=None,
+                    help="run one secondary section alone and print its JSON object (for profiling runs)")
     ap.add_argument("--scene-steps", type=int, default=240)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of 1 GiB (reference for HBM byte counters)")
@@ -241,6 +243,13 @@ def main():
     w = W.ALL[args.workload]
     sph = W.workload_spheres(w)
     sph_dev = tuple(torch.tensor(a, device=dev) for a in (sph.centers, sph.radii, sph.charges))
+    if args.only == "scene":
+        print(json.dumps({"timestep_scene": timestep_scene(dev, args.scene_steps)}), flush=True)
+        return
+    if args.only == "vc":
+        print(json.dumps({"variable_eps": variable_eps_solve(w, sph, sph_dev, dev, args.steps, args.warmup)}),
+              flush=True)
+        return
     nx, ny, nz = w.shape
     s = make_solver(w, dev, fuse=args.fuse)
     f = s.zeros()
