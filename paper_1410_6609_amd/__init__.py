@@ -245,6 +245,8 @@ class Solver:
         centers, radii = self._spheres(centers, radii)
         q = q.to(self.device, torch.float64).contiguous().reshape(-1)
         n = radii.shape[0]
+        if q.shape[0] != n:
+            raise ValueError("q and radii disagree in length")
         f = self.zeros() if out is None else self._field(out, "out")
         self._bind_stream()
         if subsample == 1 and mode == SPREAD:
@@ -273,7 +275,8 @@ class Solver:
         phi = self._field(phi, "phi")
         nx, ny, nz = self.shape
         g = torch.empty((3, nz, ny, nx), dtype=torch.float64, device=self.device) if out is None else out
-        if tuple(g.shape) != (3, nz, ny, nx) or g.dtype != torch.float64 or not g.is_contiguous():
+        if (tuple(g.shape) != (3, nz, ny, nx) or g.dtype != torch.float64 or g.device != self.device
+                or not g.is_contiguous()):
             raise ValueError("out must be a contiguous float64 tensor of shape (3, nz, ny, nx)")
         self._bind_stream()
         self._check(lib().ccmg_gradient(self._h, _ptr(phi), _ptr(g)))
@@ -286,7 +289,11 @@ class Solver:
         c, r = self._spheres(centers, radii)
         q = q.to(self.device, torch.float64).contiguous().reshape(-1)
         n = r.shape[0]
+        if q.shape[0] != n:
+            raise ValueError("q and radii disagree in length")
         F = torch.zeros((n, 3), dtype=torch.float64, device=self.device) if out is None else out
+        if tuple(F.shape) != (n, 3) or F.dtype != torch.float64 or F.device != self.device or not F.is_contiguous():
+            raise ValueError(f"out must be a contiguous float64 tensor of shape ({n}, 3) on {self.device}")
         self._bind_stream()
         self._check(lib().ccmg_coulomb_force(self._h, _ptr(phi), n, _ptr(c), _ptr(r), _ptr(q), int(subsample),
                                              int(mode), _ptr(F)))
@@ -300,6 +307,8 @@ class Solver:
         q = q.to(self.device, torch.float64).contiguous().reshape(-1)
         gF = gF.to(self.device, torch.float64).contiguous().reshape(-1, 3)
         n = r.shape[0]
+        if q.shape[0] != n or gF.shape[0] != n:
+            raise ValueError("q, gF and radii disagree in length")
         mu = self.zeros()
         direct = torch.zeros(n, dtype=torch.float64, device=self.device)
         self._bind_stream()

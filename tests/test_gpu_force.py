@@ -160,3 +160,21 @@ def test_coulomb_force_autograd_against_oracle_and_finite_differences():
         qm[t] -= step
         fd = (loss(qp) - loss(qm)) / (2 * step)
         assert abs(fd - grad[t]) <= 1e-7 * max(abs(grad[t]), 1e-3 * np.abs(grad).max()), (t, fd, grad[t])
+
+
+def test_binding_rejects_mismatched_buffers():
+    """Wrong-shaped outputs or per-sphere arrays of another length are refused
+    before any kernel is launched."""
+    s = pkg.Solver((32, 32, 32), 1.0, [(D, 0.0)] * 6, pkg.Options(levels=3), device=DEV)
+    phi = s.zeros()
+    c, r, q = to_dev([[10.0, 11.0, 12.0], [20.0, 9.0, 15.0]]), to_dev([3.0, 2.5]), to_dev([1.0, -1.0])
+    with pytest.raises(ValueError):
+        s.coulomb_force(phi, c, r, q, out=torch.zeros((1, 3), dtype=torch.float64, device=DEV))
+    with pytest.raises(ValueError):
+        s.coulomb_force(phi, c, r, to_dev([1.0]))
+    with pytest.raises(ValueError):
+        s.coulomb_adjoint(phi, c, r, q, to_dev(np.zeros((3, 3))))
+    with pytest.raises(ValueError):
+        s.gradient(phi, out=torch.zeros((3, 32, 32, 31), dtype=torch.float64, device=DEV))
+    with pytest.raises(ValueError):
+        s.deposit(c, r, to_dev([1.0, 2.0, 3.0]))
