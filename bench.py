@@ -235,8 +235,8 @@ def main():
                     help="also run one plain device copy of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs its solver on a single MI355X "
-              "(a multi-GPU decomposition is described in DESIGN.md, not built)", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver runs on a single MI355X (use --gpus 1)",
+              file=sys.stderr)
         sys.exit(2)
 
     dev = torch.device("cuda:0")
