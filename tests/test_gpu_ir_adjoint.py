@@ -198,3 +198,40 @@ def test_initial_guess_warm_start():
     phi, st = s.solve(f, rtol=1e-11)
     phi2, st2 = s.solve(f, phi.clone(), rtol=1e-10)
     assert st2.cycles == 0 and torch.equal(phi2, phi)
+
+
+def test_fp32_ir_with_face_values():
+    """Per-cell boundary values enter the FP64 fold that the refinement steps
+    use: the FP32-IR solution meets the oracle's FP64 residual bar."""
+    shape, levels, kinds, values = CASES[3]
+    h = 1.0 / shape[0]
+    s = solver(shape, levels, kinds, values, precision=pkg.FP32_IR)
+    rng = np.random.default_rng(61)
+    nx, ny, nz = shape
+    shapes = [(nz, ny)] * 2 + [(nz, nx)] * 2 + [(ny, nx)] * 2
+    faces = [rng.standard_normal(sh) if fc in (0, 3, 4) else None for fc, sh in enumerate(shapes)]
+    for fc, a in enumerate(faces):
+        if a is not None:
+            s.set_face_values(fc, to_dev(a))
+    f = rhs(shape, 62)
+    phi, st = s.solve(to_dev(f), rtol=1e-10)
+    b = oracle.fold_field(f, h, kinds, values, faces)
+    rel = oracle.norm2(oracle.residual(phi.cpu().numpy(), b, h, kinds)) / oracle.norm2(b)
+    assert st.rel_res < 1e-10 and rel < 1.0001e-10
+
+
+def test_vcycles_refinement_steps():
+    """ccmg_vcycles in FP32-IR mode: k refinement steps without host waits,
+    the residual after the last one on the device, equal to the synchronising
+    single-step path run k times."""
+    shape, levels, kinds, values = CASES[1]
+    s = solver(shape, levels, kinds, values, precision=pkg.FP32_IR)
+    f = to_dev(rhs(shape, 63))
+    a = s.zeros()
+    rel_dev = torch.zeros(1, dtype=torch.float64, device=DEV)
+    s.vcycles(a, f, 4, rel_dev)
+    b = s.zeros()
+    for _ in range(4):
+        rel = s.vcycle(b, f)
+    assert torch.equal(a, b)
+    assert float(rel_dev[0]) == rel
