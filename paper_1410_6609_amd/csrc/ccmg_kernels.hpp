@@ -251,12 +251,16 @@ constexpr int lcm_c(int a, int b) { return a / gcd_c(a, b) * b; }
 template <typename T, int SPHI, int RES, int M, int WY, int LOAD = LOAD_PHI>
 struct PassShape {
     static constexpr int S = SPHI + (RES != RES_NONE ? 1 : 0);   // stages after the load
-    static constexpr int H = (S + 1) & ~1;                           // halo, even (restriction pairs)
+    static constexpr int H = (S + 1) & ~1;                           // x halo, even (the x-pair lanes)
+    // y halo: even where the restriction pairs rows, else exactly S (a tile
+    // row may then start at an odd y; the colour parity offset is YP)
+    static constexpr int HY = RES == RES_RESTRICT ? H : S;
+    static constexpr int YP = HY & 1;
     static constexpr int EX = 64;                                    // 32 lanes x 2 cells
     static constexpr int NSTRIP = 2 * WY;
     static constexpr int EY = NSTRIP * M;
     static constexpr int TX = EX - 2 * H;
-    static constexpr int TY = EY - 2 * H;
+    static constexpr int TY = EY - 2 * HY;
     static constexpr int RP = S + 2;                                 // phi ring planes
     static constexpr int RB = S >= 4 ? RP : S + 1;                   // b ring planes
     // planes in flight: the five-stage passes have no registers to spare for a second one
@@ -278,7 +282,9 @@ template <typename T, int SPHI, int LOAD, int RES, int M, int WY>
 __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassParams<T> P)
 {
     using Sh = PassShape<T, SPHI, RES, M, WY, LOAD>;
-    constexpr int S = Sh::S, H = Sh::H, TX = Sh::TX, TY = Sh::TY, RP = Sh::RP, RB = Sh::RB, U = Sh::U;
+    constexpr int S = Sh::S, H = Sh::H, HY = Sh::HY, YP = Sh::YP, TX = Sh::TX, TY = Sh::TY, RP = Sh::RP, RB = Sh::RB,
+                  U = Sh::U;
+    static_assert(TY % 2 == 0, "tile rows must be even (the row parity of every tile is YP)");
     constexpr int NSTRIP = Sh::NSTRIP;
     static_assert(M % 2 == 0, "rows per thread must be even");
     static_assert(TX > 0 && TY > 0, "tile too small for the halo");
@@ -302,7 +308,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     const int strip = 2 * w + (lane >> 5);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int xl = bx * TX - H + 2 * xp;             // even: the pair is (xl, xl+1)
-    const int ybase = by * TY - H + strip * M;       // even
+    const int ybase = by * TY - HY + strip * M;      // parity YP
     const int z0 = bz * P.zc;
     const int z1 = min(nz, z0 + P.zc);
     const bool vx = (xl >= 0) && (xl < nx);          // nx even: both cells or neither
@@ -316,7 +322,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
         const int y = ybase + r;
         vrow[r] = vx && (y >= 0) && (y < ny);
         const int ry = strip * M + r;
-        yin[r] = (ry >= H) && (ry < H + TY);
+        yin[r] = (ry >= HY) && (ry < HY + TY);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const int x = xl + c;
@@ -358,7 +364,9 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     // stages run; they are combined (prolongation / correction) only when the
     // plane enters the ring, so no load is waited for early.
     constexpr int PD = Sh::PD;
-    T nph[PD][M][2], nbb[PD][M][2], nex[PD][M / 2];
+    // parent rows of the prolongation: rows r, r+1 share one when the tile starts at an even y
+    constexpr int NE = YP ? M : M / 2;
+    T nph[PD][M][2], nbb[PD][M][2], nex[PD][NE];
     float ncr[PD][M][2];
     auto load_plane = [&](int t, int k) {
         const bool zin = (t >= 0) && (t < nz);
@@ -377,12 +385,11 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
             if constexpr (LOAD == LOAD_CORR) { ncr[k][r][0] = c0; ncr[k][r][1] = c1; }
         }
         if constexpr (LOAD == LOAD_PROLONG) {
-            // rows r and r+1 share their parent row
 #pragma unroll
-            for (int r = 0; r < M; r += 2) {
+            for (int r = 0; r < M; r += (YP ? 1 : 2)) {
                 T e = T(0);
                 if (zin && vrow[r]) e = P.ec[((size_t)(t >> 1) * cny + ((ybase + r) >> 1)) * cnx + (xl >> 1)];
-                nex[k][r / 2] = e;
+                nex[k][YP ? r : r / 2] = e;
             }
         }
     };
@@ -404,8 +411,8 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     for (int r = 0; r < M; ++r) {
                         T v0 = nph[k][r][0], v1 = nph[k][r][1];
                         if constexpr (LOAD == LOAD_PROLONG) {
-                            v0 += P.omega * nex[k][r / 2];
-                            v1 += P.omega * nex[k][r / 2];
+                            v0 += P.omega * nex[k][YP ? r : r / 2];
+                            v1 += P.omega * nex[k][YP ? r : r / 2];
                         }
                         if constexpr (LOAD == LOAD_CORR) {
                             v0 += sig_cur * (T)ncr[k][r][0];
@@ -417,7 +424,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     if (t + PD < tend) load_plane(t + PD, k);
                     const int ppar = (S + q) & 1;
                     if constexpr (SPHI > 0) {
-                        const int o0 = (1 + 0 + ppar) & 1, o1 = (1 + (M - 1) + ppar) & 1;
+                        const int o0 = (1 + 0 + ppar + YP) & 1, o1 = (1 + (M - 1) + ppar + YP) & 1;
                         edge1[0][par][strip][0][xp] = ph[s0][0][o0];
                         edge1[0][par][strip][1][xp] = ph[s0][M - 1][o1];
                     } else if constexpr (RES != RES_NONE) {
@@ -469,7 +476,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                         constexpr bool ZB = decltype(zbt)::value;
 #pragma unroll
                         for (int r = 0; r < M; ++r) {
-                            const int o = (cs + r + ppar) & 1;
+                            const int o = (cs + r + ppar + YP) & 1;
                             T xm, xq;
                             if (o == 0) { xm = lane_prev(ph[sc][r][1]); xq = ph[sc][r][1]; }
                             else        { xm = ph[sc][r][0]; xq = lane_next(ph[sc][r][0]); }
@@ -490,7 +497,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     // keep the stages apart in the schedule (bounds register live ranges)
                     __builtin_amdgcn_sched_barrier(0);
                     if (s < SPHI) {
-                        const int o0 = (cs + 0 + ppar) & 1, o1 = (cs + (M - 1) + ppar) & 1;
+                        const int o0 = (cs + 0 + ppar + YP) & 1, o1 = (cs + (M - 1) + ppar + YP) & 1;
                         edge1[s][par][strip][0][xp] = ph[sc][0][o0];
                         edge1[s][par][strip][1][xp] = ph[sc][M - 1][o1];
                     } else if (RES != RES_NONE) {
