@@ -1328,14 +1328,21 @@ __global__ __launch_bounds__(kSphereThreads) void k_deposit_sub(const double* ce
     ball_box(cz, R, h, nz, B.k0, B.k1);
     const int bx = B.i1 - B.i0 + 1, by = B.j1 - B.j0 + 1, bz = B.k1 - B.k0 + 1;
     const long long nbox = (bx > 0 && by > 0 && bz > 0) ? (long long)bx * by * bz : 0;
-    double cnt = 0.0;
-    for (long long c = threadIdx.x; c < nbox; c += kSphereThreads) {
-        const int i = B.i0 + (int)(c % bx), j = B.j0 + (int)((c / bx) % by), k = B.k0 + (int)(c / ((long long)bx * by));
-        cnt += (double)sub_cells_in_ball<SF>(i, j, k, h, cx, cy, cz, R2);
+    // the counting pass gives W_s: needed for the spread normalisation and when
+    // the caller asks for it; the volume normalisation does without (a sphere
+    // covering no sub-cell centre then adds nothing either way)
+    double W = 0.0;
+    if (mode == 0 || weights != nullptr) {
+        double cnt = 0.0;
+        for (long long c = threadIdx.x; c < nbox; c += kSphereThreads) {
+            const int i = B.i0 + (int)(c % bx), j = B.j0 + (int)((c / bx) % by),
+                      k = B.k0 + (int)(c / ((long long)bx * by));
+            cnt += (double)sub_cells_in_ball<SF>(i, j, k, h, cx, cy, cz, R2);
+        }
+        W = block_sum_d<kSphereThreads>(cnt) / (double)(SF * SF * SF);
+        if (threadIdx.x == 0 && weights != nullptr) weights[s] = W;
+        if (W == 0.0) return;
     }
-    const double W = block_sum_d<kSphereThreads>(cnt) / (double)(SF * SF * SF);
-    if (threadIdx.x == 0 && weights != nullptr) weights[s] = W;
-    if (W == 0.0) return;
     const double norm = sphere_norm(mode, eps, W, R, h);
     const double qs = q[s];
     for (long long c = threadIdx.x; c < nbox; c += kSphereThreads) {
