@@ -5,7 +5,7 @@ in HBM: charge deposition of the spheres, boundary folding of the right-hand
 side and the multigrid solve from phi = 0 to ||b - A phi|| / ||b|| < 1e-10.
 Workload (default): 256^3 cells, Dirichlet phi = 0 / 1 on the z faces and
 zero-Neumann sides, 200 seeded charged spheres of radius 4, plain FP64
-V(2,2)-cycles down to an 8^3 coarsest grid.
+V(2,2)-cycles (correction factor 1.95) down to an 8^3 coarsest grid.
 
 Prints one JSON line.  Also reports the FP32-in-FP64 refinement solve on the
 same input, the live-timed roofline of the dominant kernel and the CPU
@@ -311,6 +311,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded charged spheres)",
         "config": {"workload": w.name, "cells": [nx, ny, nz], "levels": s.levels, "cycle": "V(2,2)",
+                   "omega": w.omega,
                    "coarsest": list(s.level_dims(s.levels - 1)), "rtol": w.rtol, "spheres": w.n_spheres,
                    "precision": "fp64", "fused_sweeps_per_pass": args.fuse},
         "cycles": st.cycles,

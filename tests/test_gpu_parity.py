@@ -205,3 +205,38 @@ def test_deposit_empty_and_tiny_spheres():
     c = np.array([[0.5 / 32 * 2, 0.5 / 32 * 2, 0.5 / 32 * 2]])
     f, cnt = s.deposit(to_dev(c), to_dev([1e-4]), to_dev([1.0]), counts=True)
     assert int(cnt[0]) == 0 and not f.any()
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[3]], ids=ids)
+def test_solve_parity_workload_omega(case):
+    """The workloads' correction factor (1.95): same cycles and iterates as the
+    oracle with the same factor."""
+    shape, levels, kinds, values = case
+    om = W.C2.omega
+    s = solver_for(shape, levels, kinds, values, omega=om)
+    h = 1.0 / shape[0]
+    f = rhs(shape, 17)
+    phi, st = s.solve(to_dev(f), rtol=1e-10)
+    ref, hist, ost = oracle.solve(oracle.fold(f, h, kinds, values), h, kinds, levels, omega=om, rtol=1e-10)
+    assert ost == 0 and st.cycles == len(hist) - 1
+    assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_benchmark_configuration_full_size():
+    """The benchmark's own step at full size (256^3, 200 spheres, omega 1.95):
+    same cycle count as the oracle and the oracle's residual of the GPU
+    solution below the tolerance."""
+    w = W.C2
+    sph = W.workload_spheres(w)
+    log_case("bench config", w.shape)
+    s = pkg.Solver(w.shape, w.h, list(zip(w.kinds, w.values)), pkg.Options(levels=w.levels, omega=w.omega),
+                   device=DEV)
+    f = s.deposit(to_dev(sph.centers), to_dev(sph.radii), to_dev(sph.charges), w.eps)
+    phi, st = s.solve(f, rtol=w.rtol)
+    fr, _ = oracle.deposit(w.shape, w.h, sph.centers, sph.radii, sph.charges, w.eps)
+    b = oracle.fold(fr, w.h, w.kinds, w.values)
+    ref, hist, _ = oracle.solve(b, w.h, w.kinds, w.levels, omega=w.omega, rtol=w.rtol)
+    assert st.cycles == len(hist) - 1 == 12
+    got = phi.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert oracle.norm2(oracle.residual(got, b, w.h, w.kinds)) / oracle.norm2(b) < w.rtol
