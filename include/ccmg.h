@@ -107,14 +107,18 @@ void ccmg_default_options(ccmg_options* opt);
  * defaults.  hip_stream is a hipStream_t (NULL = null stream).  Builds the
  * level hierarchy on the host (Sec. 3: a level is coarsened by 2x2x2 while the
  * cell counts per dimension stay even); touches no device memory.
- * Errors: E_ARG (null out/bc, h <= 0, bad kinds or options), E_DIMS (a dim not
- * divisible by 2^(levels-1), coarsest grid over CCMG_MAX_COARSE_CELLS cells),
- * E_SINGULAR (all six faces Neumann). */
+ * Errors: E_ARG (null out/bc, h <= 0, bad kinds or options, an unpaired
+ * periodic face, FP32-IR with variable permittivity or a periodic axis),
+ * E_DIMS (a dim not divisible by 2^(levels-1), coarsest grid over
+ * CCMG_MAX_COARSE_CELLS cells), E_SINGULAR (no Dirichlet face: every face
+ * Neumann or periodic). */
 int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_face bc[6],
                 const ccmg_options* opt, void* hip_stream);
 
 /* Bytes of device workspace the solver needs (hierarchy arrays, ping-pong
- * buffers, norm partials and the control block). */
+ * buffers, norm partials, the control block, per-cell boundary values and,
+ * with variable permittivity or a periodic axis, the face coefficients of
+ * every level). */
 size_t ccmg_workspace_bytes(const ccmg_solver* s);
 
 /* Attach caller-owned device memory of at least ccmg_workspace_bytes() bytes,
