@@ -252,10 +252,13 @@ template <typename T, int SPHI, int RES, int M, int WY, int LOAD = LOAD_PHI>
 struct PassShape {
     static constexpr int S = SPHI + (RES != RES_NONE ? 1 : 0);   // stages after the load
     static constexpr int H = (S + 1) & ~1;                           // x halo, even (the x-pair lanes)
-    // y halo: even where the restriction pairs rows, else exactly S (a tile
-    // row may then start at an odd y; the colour parity offset is YP)
-    static constexpr int HY = RES == RES_RESTRICT ? H : S;
+    // y halo: exactly S rows; a tile then starts at an odd y when S is odd
+    // (the colour parity offset YP), and the restriction pairs rows across
+    // neighbouring strips.  FP32 restriction passes keep the even halo: their
+    // 64-row tiles gain no tile from it and the extra registers spill.
+    static constexpr int HY = (RES == RES_RESTRICT && sizeof(T) == 4) ? H : S;
     static constexpr int YP = HY & 1;
+    static constexpr bool XSTRIP_RESTRICT = RES == RES_RESTRICT && YP == 1;
     static constexpr int EX = 64;                                    // 32 lanes x 2 cells
     static constexpr int NSTRIP = 2 * WY;
     static constexpr int EY = NSTRIP * M;
@@ -295,6 +298,9 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     __shared__ T edge1[Sh::E1][2][NSTRIP][2][32];
     // both cells of the edge rows, input of the residual stage
     __shared__ T edge2[RES != RES_NONE ? 2 : 1][NSTRIP][2][32][2];
+    // restriction across strips (odd first row): row-0 pair sums, by step parity
+    __shared__ T rq[Sh::XSTRIP_RESTRICT ? 2 : 1][NSTRIP][32];
+    static_assert(!Sh::XSTRIP_RESTRICT || M == 2, "cross-strip restriction pairs row 1 with the next strip's row 0");
 
     const int nblk = P.tiles_x * P.tiles_y * P.zchunks;
     const int blk = xcd_block_id(nblk);
@@ -394,7 +400,10 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
         }
     };
 
-    const int tbeg = z0 - S, tend = z1 + S;     // tbeg has the parity of S (z0 is even)
+    // tbeg has the parity of S (z0 is even); a cross-strip restriction
+    // finishes each plane one step after its residual, hence one more step
+    const int tbeg = z0 - S, tend = z1 + S + (Sh::XSTRIP_RESTRICT ? 1 : 0);
+    T q1p = T(0);                                   // row-1 pair sum of the previous step's plane
 #pragma unroll
     for (int k = 0; k < PD; ++k) load_plane(tbeg + k, k);
 
@@ -519,6 +528,20 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                                        ph[so][r][1]);
                     }
                 }
+                // ---- restriction across strips of the plane whose residual the
+                // previous step computed: children rows y (this thread's row 1) and
+                // y + 1 (the next strip's row 0), planes paired in z as above
+                if constexpr (Sh::XSTRIP_RESTRICT) if (t - 1 - S >= z0 && t - 1 - S < z1) {
+                    const int pp = t - 1 - S;
+                    const T q0n = strip < NSTRIP - 1 ? rq[par ^ 1][strip + 1][xp] : T(0);
+                    const T s4 = q1p + q0n;
+                    if ((pp & 1) == 0) {
+                        racc[0] = s4;
+                    } else if (xin && vrow[1] && yin[1]) {
+                        P.bc_out[((size_t)(pp >> 1) * cny + ((ybase + 1) >> 1)) * cnx + (xl >> 1)] =
+                            T(0.25) * (racc[0] + s4);
+                    }
+                }
                 // ---- residual stage at plane t - S (both cells of every pair)
                 if constexpr (RES != RES_NONE) if (t - S >= z0 && t - S < z1) {
                     const int p = t - S;
@@ -547,7 +570,12 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                             res[r][c] = bb[sb][r][c] - (T(dxy[r][c] + dz) * ph[sc][r][c] - sum);
                         }
                     }
-                    if constexpr (RES == RES_RESTRICT) {
+                    if constexpr (Sh::XSTRIP_RESTRICT) {
+                        // row 0 (odd y) pairs with the previous strip's row 1, row 1 with
+                        // the next strip's row 0: publish row 0, keep row 1 for the next step
+                        rq[par][strip][xp] = res[0][0] + res[0][1];
+                        q1p = res[1][0] + res[1][1];
+                    } else if constexpr (RES == RES_RESTRICT) {
                         // children: the pair (x), rows r, r+1 (y), planes p, p+1 (z)
                         const bool writer = pok && xin;
 #pragma unroll
