@@ -264,7 +264,10 @@ struct PassShape {
     static constexpr int EY = NSTRIP * M;
     static constexpr int TX = EX - 2 * H;
     static constexpr int TY = EY - 2 * HY;
-    static constexpr int RP = S + 2;                                 // phi ring planes
+    // phi ring: S + 2 planes are live; an even ring keeps the unrolled step
+    // count U (a multiple of the ring lengths and of the colour period 2)
+    // small, so the loop body stays well inside the instruction cache
+    static constexpr int RP = (S + 3) & ~1;
     static constexpr int RB = S >= 4 ? RP : S + 1;                   // b ring planes
     // planes in flight: the five-stage passes have no registers to spare for a second one
     static constexpr int PD = CCMG_PREFETCH;
@@ -374,7 +377,23 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     constexpr int NE = YP ? M : M / 2;
     T nph[PD][M][2], nbb[PD][M][2], nex[PD][NE];
     float ncr[PD][M][2];
-    auto load_plane = [&](int t, int k) {
+    // parent values of plane t (zero outside the domain)
+    auto load_parents = [&](int t, T* e) {
+        const bool zin = (t >= 0) && (t < nz);
+#pragma unroll
+        for (int r = 0; r < M; r += (YP ? 1 : 2)) {
+            T v = T(0);
+            if (zin && vrow[r]) v = P.ec[((size_t)(t >> 1) * cny + ((ybase + r) >> 1)) * cnx + (xl >> 1)];
+            e[YP ? r : r / 2] = v;
+        }
+    };
+    // The two planes 2k, 2k+1 share their parent plane: an odd plane reuses
+    // the parents of the even plane below it (kept in elast), so only even
+    // planes load them.  The parity of a plane is fixed by its unrolled step.
+    T elast[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) elast[i] = T(0);
+    auto load_plane = [&](int t, int k, auto oddt) {
         const bool zin = (t >= 0) && (t < nz);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
@@ -390,14 +409,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
             nbb[k][r][0] = b0; nbb[k][r][1] = b1;
             if constexpr (LOAD == LOAD_CORR) { ncr[k][r][0] = c0; ncr[k][r][1] = c1; }
         }
-        if constexpr (LOAD == LOAD_PROLONG) {
-#pragma unroll
-            for (int r = 0; r < M; r += (YP ? 1 : 2)) {
-                T e = T(0);
-                if (zin && vrow[r]) e = P.ec[((size_t)(t >> 1) * cny + ((ybase + r) >> 1)) * cnx + (xl >> 1)];
-                nex[k][YP ? r : r / 2] = e;
-            }
-        }
+        if constexpr (LOAD == LOAD_PROLONG && !decltype(oddt)::value) load_parents(t, nex[k]);
     };
 
     // tbeg has the parity of S (z0 is even); a cross-strip restriction
@@ -405,7 +417,12 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     const int tbeg = z0 - S, tend = z1 + S + (Sh::XSTRIP_RESTRICT ? 1 : 0);
     T q1p = T(0);                                   // row-1 pair sum of the previous step's plane
 #pragma unroll
-    for (int k = 0; k < PD; ++k) load_plane(tbeg + k, k);
+    for (int k = 0; k < PD; ++k) {
+        if ((S + k) & 1) load_plane(tbeg + k, k, std::true_type{});
+        else load_plane(tbeg + k, k, std::false_type{});
+    }
+    // the first plane is odd when S is: its parents are those of plane tbeg - 1
+    if constexpr (LOAD == LOAD_PROLONG && (S & 1)) load_parents(tbeg - 1, elast);
 
     for (int tb = tbeg; tb < tend; tb += U) {
 #pragma unroll
@@ -416,12 +433,18 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                 // ---- stage 0: the prefetched plane t enters the rings; plane t+PD is requested
                 {
                     const int s0 = q % RP, sb0 = q % RB, k = q % PD;
+                    if constexpr (LOAD == LOAD_PROLONG) {
+                        if (((S + q) & 1) == 0) {
+#pragma unroll
+                            for (int i = 0; i < NE; ++i) elast[i] = nex[k][i];
+                        }
+                    }
 #pragma unroll
                     for (int r = 0; r < M; ++r) {
                         T v0 = nph[k][r][0], v1 = nph[k][r][1];
                         if constexpr (LOAD == LOAD_PROLONG) {
-                            v0 += P.omega * nex[k][YP ? r : r / 2];
-                            v1 += P.omega * nex[k][YP ? r : r / 2];
+                            v0 += P.omega * elast[YP ? r : r / 2];
+                            v1 += P.omega * elast[YP ? r : r / 2];
                         }
                         if constexpr (LOAD == LOAD_CORR) {
                             v0 += sig_cur * (T)ncr[k][r][0];
@@ -430,7 +453,10 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                         ph[s0][r][0] = v0; ph[s0][r][1] = v1;
                         bb[sb0][r][0] = nbb[k][r][0]; bb[sb0][r][1] = nbb[k][r][1];
                     }
-                    if (t + PD < tend) load_plane(t + PD, k);
+                    if (t + PD < tend) {
+                        if ((S + q + PD) & 1) load_plane(t + PD, k, std::true_type{});
+                        else load_plane(t + PD, k, std::false_type{});
+                    }
                     const int ppar = (S + q) & 1;
                     if constexpr (SPHI > 0) {
                         const int o0 = (1 + 0 + ppar + YP) & 1, o1 = (1 + (M - 1) + ppar + YP) & 1;
@@ -481,28 +507,33 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     if (p < z0 - (S - s) || p >= z1 + (S - s)) continue;
                     const T elo = e_lo[s - 1];
                     const T ehi = e_hi[s - 1];
-                    auto body = [&](auto zbt) {
-                        constexpr bool ZB = decltype(zbt)::value;
+                    // 1/diagonal of the updated cell of each row; planes at a z face
+                    // (dz != 0, uniform over the workgroup) take a short branch that
+                    // recomputes it, so the update itself exists once in the code
+                    T invz[M];
+#pragma unroll
+                    for (int r = 0; r < M; ++r) invz[r] = inv0[r][(cs + r + ppar + YP) & 1];
+                    if (dz != 0) {
 #pragma unroll
                         for (int r = 0; r < M; ++r) {
                             const int o = (cs + r + ppar + YP) & 1;
-                            T xm, xq;
-                            if (o == 0) { xm = lane_prev(ph[sc][r][1]); xq = ph[sc][r][1]; }
-                            else        { xm = ph[sc][r][0]; xq = lane_next(ph[sc][r][0]); }
-                            const T ym = r > 0 ? ph[sc][r - 1][o] : elo;
-                            const T yp = r < M - 1 ? ph[sc][r + 1][o] : ehi;
-                            const T sum = ((((xm + xq) + ym) + yp) + ph[sm][r][o]) + ph[sp][r][o];
-                            T inv;
-                            if constexpr (ZB) inv = vrow[r] ? T(1) / T(dxy[r][o] + dz) : T(0);
-                            else inv = inv0[r][o];
-                            // cells outside the domain have inv = 0, planes outside it stay zero
-                            const T nv = (bb[sb][r][o] + sum) * inv;
-                            if constexpr (Sh::MASKED_UPDATE) ph[sc][r][o] = (pin && vrow[r]) ? nv : ph[sc][r][o];
-                            else ph[sc][r][o] = pin ? nv : T(0);
+                            invz[r] = vrow[r] ? T(1) / T(dxy[r][o] + dz) : T(0);
                         }
-                    };
-                    if (dz != 0) body(std::true_type{});
-                    else body(std::false_type{});
+                    }
+#pragma unroll
+                    for (int r = 0; r < M; ++r) {
+                        const int o = (cs + r + ppar + YP) & 1;
+                        T xm, xq;
+                        if (o == 0) { xm = lane_prev(ph[sc][r][1]); xq = ph[sc][r][1]; }
+                        else        { xm = ph[sc][r][0]; xq = lane_next(ph[sc][r][0]); }
+                        const T ym = r > 0 ? ph[sc][r - 1][o] : elo;
+                        const T yp = r < M - 1 ? ph[sc][r + 1][o] : ehi;
+                        const T sum = ((((xm + xq) + ym) + yp) + ph[sm][r][o]) + ph[sp][r][o];
+                        // cells outside the domain have inv = 0, planes outside it stay zero
+                        const T nv = (bb[sb][r][o] + sum) * invz[r];
+                        if constexpr (Sh::MASKED_UPDATE) ph[sc][r][o] = (pin && vrow[r]) ? nv : ph[sc][r][o];
+                        else ph[sc][r][o] = pin ? nv : T(0);
+                    }
                     // keep the stages apart in the schedule (bounds register live ranges)
                     __builtin_amdgcn_sched_barrier(0);
                     if (s < SPHI) {
