@@ -217,9 +217,13 @@ bool launch_one(const PassParams<T>& P0, hipStream_t st)
     P.tiles_y = g.tiles_y;
     P.zchunks = g.zchunks;
     P.zc = g.zc;
-    // the norm reduction stores one partial per block
-    if ((RES == RES_NORM || RES == RES_NORM_R32 || RES == RES_STORE) && g.blocks() > P.max_partials) return false;
+    // the norm reduction stores one partial per block, then one workgroup adds them
+    constexpr bool kNormRes = RES == RES_NORM || RES == RES_NORM_R32 || RES == RES_STORE;
+    if (kNormRes && g.blocks() > P.max_partials) return false;
     hipLaunchKernelGGL(kern, dim3(g.blocks()), dim3(64 * WYT), 0, st, P);
+    if constexpr (kNormRes)
+        hipLaunchKernelGGL(k_finish_norm<64 * WYT>, dim3(1), dim3(64 * WYT), 0, st, (const double*)P.partials,
+                           g.blocks(), P.ctl, P.fin, P.cycle, 1);
     return true;
 }
 
@@ -579,6 +583,8 @@ int enqueue_vc_norm(ccmg_solver* s, const double* phi, int fin, double* r_out, d
     const int g = std::max(1, std::min(vc_grid(s->lv[0].n), s->max_partials));
     hipLaunchKernelGGL(k_vc_norm, dim3(g), dim3(kVcNormThreads), 0, s->stream, vc_level(s, 0), phi,
                        (const double*)s->lv[0].b, r_out, rscale, s->partials, s->ctl, fin, cycle);
+    hipLaunchKernelGGL(k_finish_norm<kVcNormThreads>, dim3(1), dim3(kVcNormThreads), 0, s->stream,
+                       (const double*)s->partials, g, s->ctl, fin, cycle, fin == FIN_CYCLE ? 1 : 0);
     LAUNCHCHK(s);
     return CCMG_OK;
 }
@@ -668,7 +674,7 @@ int enqueue_norm(ccmg_solver* s, const double* phi, int fin, int res, double* r_
 struct CtlHead {
     double rtol, bnorm, rnorm, rel, sig_cur, sig_next;
     int done, status, cycles, bzero;
-    unsigned counter;
+    unsigned reserved;
     int cg_iters;
     int pad[2];
 };

@@ -44,7 +44,7 @@ struct Ctl {
     int status;         // 0 or -5 (non-finite)
     int cycles;         // index of the last finished cycle
     int bzero;          // ||b|| == 0
-    unsigned int counter;  // blocks finished in the current reduction
+    unsigned int reserved;  // unused (keeps the layout)
     int cg_iters;       // iterations of the last coarsest-grid CG
     int pad[2];
     double hist[kMaxHist];
@@ -107,15 +107,17 @@ __device__ __forceinline__ int xcd_block_id(int nblk)
     return xcd < rem ? xcd * (q + 1) + k : rem * (q + 1) + (xcd - rem) * q + k;
 }
 
-// Last-block reduction epilogue.  Every block stores its two partial sums;
-// the block that finishes last adds all partials in block order (deterministic)
-// and updates the control block.
+// Norm reductions take two kernels.  The producer's blocks each store the
+// sums of r^2 and b^2 over their cells (partials[2 blk], partials[2 blk + 1]);
+// k_finish_norm, launched next on the same stream, adds them in block order
+// (deterministic) and updates the control block.  The kernel boundary orders
+// the partials before their reads: no device-scope fence or arrival counter in
+// the producer, whose blocks would otherwise each write back their XCD's L2
+// and serialise on one atomic.
 template <int NT>
-__device__ void finish_norm(double s_r2, double s_b2, double* partials, Ctl* ctl, int fin, int cycle,
-                            int nblk, int myblk)
+__device__ void store_partials(double s_r2, double s_b2, double* partials, int myblk)
 {
     __shared__ double red[2][NT / 64];
-    __shared__ int last;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     s_r2 = wave_sum(s_r2);
     s_b2 = wave_sum(s_b2);
@@ -126,28 +128,31 @@ __device__ void finish_norm(double s_r2, double s_b2, double* partials, Ctl* ctl
         for (int i = 0; i < NT / 64; ++i) { a += red[0][i]; b += red[1][i]; }
         partials[2 * myblk] = a;
         partials[2 * myblk + 1] = b;
-        __threadfence();
-        const unsigned prev = atomicAdd(&ctl->counter, 1u);
-        last = (prev == (unsigned)nblk - 1u);
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+// One workgroup of NT threads.  gate != 0: nothing to do when ctl->done was
+// already set before the producer ran (the producer then returned at once).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_finish_norm(const double* partials, int nblk, Ctl* ctl, int fin, int cycle,
+                                                     int gate)
+{
+    if (gate && ctl->done) return;
+    __shared__ double red[2][NT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     double a = 0.0, b = 0.0;
     for (int i = tid; i < nblk; i += NT) {
-        a += __hip_atomic_load(&partials[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        b += __hip_atomic_load(&partials[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a += partials[2 * i];
+        b += partials[2 * i + 1];
     }
     a = wave_sum(a);
     b = wave_sum(b);
-    __syncthreads();
     if (lane == 0) { red[0][w] = a; red[1][w] = b; }
     __syncthreads();
     if (tid != 0) return;
     double r2 = 0.0, b2 = 0.0;
     for (int i = 0; i < NT / 64; ++i) { r2 += red[0][i]; b2 += red[1][i]; }
     const double rn = sqrt(r2), bn = sqrt(b2);
-    ctl->counter = 0u;
     ctl->rnorm = rn;
     // a NaN/Inf anywhere in b or the residual makes one of the sums non-finite
     const bool finite = isfinite(rn) && isfinite(bn);
@@ -644,7 +649,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     }
 
     if constexpr (RES == RES_NORM || RES == RES_NORM_R32 || RES == RES_STORE) {
-        finish_norm<64 * WY>(acc_r2, acc_b2, P.partials, P.ctl, P.fin, P.cycle, nblk, blk);
+        store_partials<64 * WY>(acc_r2, acc_b2, P.partials, blk);
     }
 }
 
@@ -787,6 +792,25 @@ __device__ __forceinline__ int padded(int i, int j, int k, int nx, int ny)
     return ((k + 1) * (ny + 2) + (j + 1)) * (nx + 2) + (i + 1);
 }
 
+// floor(c / d) for 0 <= c < 2^16 and 1 <= d < 2^16 by one high multiply with
+// m = ceil(2^32 / d): c m / 2^32 exceeds c / d by less than c / 2^32 < 1 / d,
+// too little to reach the next integer.  Replaces the long integer division
+// sequence in the index arithmetic of the small-grid kernels.
+struct SmallDiv {
+    unsigned d, m;
+    __device__ explicit SmallDiv(int den) : d((unsigned)den), m(den > 1 ? 0xFFFFFFFFu / (unsigned)den + 1u : 0u) {}
+    __device__ __forceinline__ int div(int c) const { return d > 1 ? (int)__umulhi((unsigned)c, m) : c; }
+};
+
+// (i, j, k) of the plain index c = (k ny + j) nx + i, with dx = nx, dy = ny
+__device__ __forceinline__ void split3(int c, const SmallDiv& dx, const SmallDiv& dy, int& i, int& j, int& k)
+{
+    const int q = dx.div(c);
+    i = c - q * (int)dx.d;
+    k = dy.div(q);
+    j = q - k * (int)dy.d;
+}
+
 __device__ __forceinline__ int cell_diag(int i, int j, int k, int nx, int ny, int nz, const int* sh)
 {
     int d = 6;
@@ -853,11 +877,13 @@ __device__ int cg_one_wave(GetB get_b, PutX put_x, double* rl, int nx, int ny, i
     const int sy = nx + 2, sz = (nx + 2) * (ny + 2);
     double xr[NPT], rv[NPT], pv[NPT], sv[NPT];
     int pc_[NPT], dg[NPT];
+    const SmallDiv dx(nx), dy(ny);
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int c = lane + 64 * k;
         const bool v = c < n;
-        const int i = v ? c % nx : 0, j = v ? (c / nx) % ny : 0, kk = v ? c / (nx * ny) : 0;
+        int i, j, kk;
+        split3(v ? c : 0, dx, dy, i, j, kk);
         dg[k] = v ? cell_diag(i, j, kk, nx, ny, nz, sh) : 0;
         // lanes without a cell point at the corner ghost (index 0): they read
         // zeros and only ever store their residual, which stays 0
@@ -868,58 +894,59 @@ __device__ int cg_one_wave(GetB get_b, PutX put_x, double* rl, int nx, int ny, i
         rv[k] = v ? (double)get_b(c) : 0.0;
         if (v) rl[pc_[k]] = rv[k];
     }
-    double gamma = 0.0, dummy = 0.0;
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) gamma += rv[k] * rv[k];
-    wave_sum2_dpp(gamma, dummy);
-    const double bound = rtol * rtol * gamma;     // ||r||^2 <= rtol^2 ||b||^2
-    double gamma_old = 1.0, alpha_old = 1.0;
+    // Each iteration reduces (r, r) and (r, S r) of the current residual in one
+    // combined wave sum; the stopping test on (r, r) therefore sits at the top
+    // of the next iteration, after its matrix product (one spare product at
+    // the end).  Sums and their order are those of the two-reduction form.
+    double gamma_old = 1.0, alpha_old = 1.0, bound = 0.0;
     int it = 0;
-    if (gamma > 0.0) {
-        while (it < maxit) {
-            // w = S r, delta = (w, r); gamma = (r, r) is already known
-            double wv[NPT], nbs[NPT][6];
-            double delta = 0.0;
-            // all neighbour loads first (unconditional), then the arithmetic
+    while (true) {
+        // w = S r, gamma = (r, r), delta = (w, r)
+        double wv[NPT], nbs[NPT][6];
+        double gamma = 0.0, delta = 0.0;
+        // all neighbour loads first (unconditional), then the arithmetic
 #pragma unroll
-            for (int k = 0; k < NPT; ++k) {
-                const int c = dg[k] ? pc_[k] : sz + sy + 1;   // a ghost-surrounded safe index
-                nbs[k][0] = rl[c - 1];
-                nbs[k][1] = rl[c + 1];
-                nbs[k][2] = rl[c - sy];
-                nbs[k][3] = rl[c + sy];
-                nbs[k][4] = rl[c - sz];
-                nbs[k][5] = rl[c + sz];
-            }
-#pragma unroll
-            for (int k = 0; k < NPT; ++k) {
-                const double sum = ((((nbs[k][0] + nbs[k][1]) + nbs[k][2]) + nbs[k][3]) + nbs[k][4]) + nbs[k][5];
-                const double mask = dg[k] ? 1.0 : 0.0;
-                wv[k] = mask * ((double)dg[k] * rv[k] - sum);
-                delta += rv[k] * wv[k];
-            }
-            wave_sum2_dpp(delta, dummy);
-            const double beta = it == 0 ? 0.0 : gamma * fast_rcp(gamma_old);
-            const double alpha = gamma * fast_rcp(delta - beta * gamma * fast_rcp(alpha_old));
-            double g2 = 0.0, d2 = 0.0;
-            __builtin_amdgcn_wave_barrier();   // all lanes' reads of r precede its update below
-#pragma unroll
-            for (int k = 0; k < NPT; ++k) {
-                pv[k] = rv[k] + beta * pv[k];
-                sv[k] = wv[k] + beta * sv[k];
-                xr[k] += alpha * pv[k];
-                rv[k] -= alpha * sv[k];
-                g2 += rv[k] * rv[k];
-                rl[pc_[k]] = rv[k];
-            }
-            __builtin_amdgcn_wave_barrier();
-            wave_sum2_dpp(g2, d2);
-            ++it;
-            gamma_old = gamma;
-            alpha_old = alpha;
-            gamma = g2;
-            if (gamma <= bound) break;
+        for (int k = 0; k < NPT; ++k) {
+            const int c = dg[k] ? pc_[k] : sz + sy + 1;   // a ghost-surrounded safe index
+            nbs[k][0] = rl[c - 1];
+            nbs[k][1] = rl[c + 1];
+            nbs[k][2] = rl[c - sy];
+            nbs[k][3] = rl[c + sy];
+            nbs[k][4] = rl[c - sz];
+            nbs[k][5] = rl[c + sz];
         }
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) gamma += rv[k] * rv[k];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const double sum = ((((nbs[k][0] + nbs[k][1]) + nbs[k][2]) + nbs[k][3]) + nbs[k][4]) + nbs[k][5];
+            const double mask = dg[k] ? 1.0 : 0.0;
+            wv[k] = mask * ((double)dg[k] * rv[k] - sum);
+            delta += rv[k] * wv[k];
+        }
+        wave_sum2_dpp(gamma, delta);
+        if (it == 0) {
+            if (!(gamma > 0.0)) break;                // b = 0: x = 0
+            bound = rtol * rtol * gamma;              // ||r||^2 <= rtol^2 ||b||^2
+        } else if (gamma <= bound) {
+            break;
+        }
+        if (it >= maxit) break;
+        const double beta = it == 0 ? 0.0 : gamma * fast_rcp(gamma_old);
+        const double alpha = gamma * fast_rcp(delta - beta * gamma * fast_rcp(alpha_old));
+        __builtin_amdgcn_wave_barrier();   // all lanes' reads of r precede its update below
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            pv[k] = rv[k] + beta * pv[k];
+            sv[k] = wv[k] + beta * sv[k];
+            xr[k] += alpha * pv[k];
+            rv[k] -= alpha * sv[k];
+            rl[pc_[k]] = rv[k];
+        }
+        __builtin_amdgcn_wave_barrier();
+        ++it;
+        gamma_old = gamma;
+        alpha_old = alpha;
     }
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -1001,13 +1028,15 @@ __device__ void bottom_smooth(T* ph, const T* bt, int nx, int ny, int nz, const 
     const int hx = nx / 2, half = hx * ny * nz;   // nx even: each colour has half the cells
     const int sy = nx + 2, sz = (nx + 2) * (ny + 2);
     int pidx[2][kBottomCpt], bidx[2][kBottomCpt], dg[2][kBottomCpt];
+    const SmallDiv dhx(hx), dny(ny);
 #pragma unroll
     for (int colour = 0; colour < 2; ++colour)
 #pragma unroll
         for (int u = 0; u < kBottomCpt; ++u) {
             const int m = threadIdx.x + u * kBottomThreads;
             const bool v = m < half;
-            const int ip = v ? m % hx : 0, j = v ? (m / hx) % ny : 0, k = v ? m / (hx * ny) : 0;
+            int ip, j, k;
+            split3(v ? m : 0, dhx, dny, ip, j, k);
             const int i = 2 * ip + ((j + k + colour) & 1);   // entries without a cell only load (cell 0 or 1)
             pidx[colour][u] = padded(i, j, k, nx, ny);
             bidx[colour][u] = (k * ny + j) * nx + i;
@@ -1066,8 +1095,10 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomParams<T>
         const int cnx = nx / 2, cny = ny / 2, cnz = nz / 2, nc = cnx * cny * cnz;
         const int sy = nx + 2, sz = (nx + 2) * (ny + 2);
         T* bc = b_all + P.boff[l + 1];
+        const SmallDiv dcx(cnx), dcy(cny);
         for (int C = threadIdx.x; C < nc; C += kBottomThreads) {
-            const int I = C % cnx, J = (C / cnx) % cny, K = C / (cnx * cny);
+            int I, J, K;
+            split3(C, dcx, dcy, I, J, K);
             T acc[2][2];
 #pragma unroll
             for (int dk = 0; dk < 2; ++dk)
@@ -1094,10 +1125,12 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomParams<T>
         const int nx = P.nx[lc], ny = P.ny[lc];
         const T* bt = b_all + P.boff[lc];
         T* ph = ph_all + P.poff[lc];
+        const SmallDiv dx(nx), dy(ny);
         const int it = cg_one_wave(
             [&](int c) { return bt[c]; },
             [&](int c, double v) {
-                const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+                int i, j, k;
+                split3(c, dx, dy, i, j, k);
                 ph[padded(i, j, k, nx, ny)] = (T)v;
             },
             pl, nx, ny, P.nz[lc], P.sh, P.cg_rtol, P.cg_maxit);
@@ -1110,8 +1143,10 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomParams<T>
         const int cnx = nx / 2, cny = ny / 2;
         T* ph = ph_all + P.poff[l];
         const T* pc = ph_all + P.poff[l + 1];
+        const SmallDiv dx(nx), dy(ny);
         for (int c = threadIdx.x; c < n; c += kBottomThreads) {
-            const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+            int i, j, k;
+            split3(c, dx, dy, i, j, k);
             ph[padded(i, j, k, nx, ny)] += P.omega * pc[padded(i >> 1, j >> 1, k >> 1, cnx, cny)];
         }
         __syncthreads();
@@ -1120,8 +1155,10 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomParams<T>
     {
         const int nx = P.nx[0], ny = P.ny[0];
         const T* ph = ph_all + P.poff[0];
+        const SmallDiv dx(nx), dy(ny);
         for (int c = threadIdx.x; c < n0; c += kBottomThreads) {
-            const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+            int i, j, k;
+            split3(c, dx, dy, i, j, k);
             P.phi_out[c] = ph[padded(i, j, k, nx, ny)];
         }
     }
@@ -1216,7 +1253,7 @@ __global__ void k_ctl_init(Ctl* ctl, double rtol)
         ctl->status = 0;
         ctl->cycles = 0;
         ctl->bzero = 0;
-        ctl->counter = 0u;
+        ctl->reserved = 0u;
         ctl->cg_iters = 0;
     }
 }
@@ -1736,6 +1773,33 @@ struct VcLevel {
     int per[3];   // periodic axes: the boundary face couples cell n-1 and cell 0
 };
 
+// Cell coordinates of a grid-stride loop over c = (k ny + j) nx + i: the start
+// and the stride are split once, then every step adds the stride's (i, j, k)
+// parts with carries, so the loop body divides nothing (a 64-bit division per
+// cell would dominate these memory-light kernels).
+struct Walk3 {
+    int i, j, k;
+    int si, sj, sk, nx, ny;
+    __device__ Walk3(size_t c0, size_t stride, int nx_, int ny_) : nx(nx_), ny(ny_)
+    {
+        const size_t pl = (size_t)nx * ny;
+        i = (int)(c0 % nx);
+        j = (int)((c0 / nx) % ny);
+        k = (int)(c0 / pl);
+        si = (int)(stride % nx);
+        sj = (int)((stride / nx) % ny);
+        sk = (int)(stride / pl);
+    }
+    __device__ __forceinline__ void next()
+    {
+        i += si;          // < 2 nx: at most one carry
+        j += sj;
+        k += sk;
+        if (i >= nx) { i -= nx; ++j; }
+        if (j >= ny) { j -= ny; ++k; }   // j <= 2 ny - 1 before
+    }
+};
+
 __device__ __forceinline__ size_t vc_ix(const VcLevel& L, int i, int j, int k)
 {
     return ((size_t)k * L.ny + j) * (size_t)(L.nx + 1) + i;
@@ -1853,8 +1917,10 @@ __global__ void k_vc_fold(VcFold P, VcLevel L)
 {
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const size_t n = (size_t)nx * ny * nz;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+    const size_t c0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    Walk3 w(c0, stride, nx, ny);
+    for (size_t c = c0; c < n; c += stride, w.next()) {
+        const int i = w.i, j = w.j, k = w.k;
         double v = P.f[c];
         if (i == 0) v += vc_bterm(P, L, 0, (size_t)k * ny + j, L.kx[vc_ix(L, 0, j, k)]);
         if (i == nx - 1) v += vc_bterm(P, L, 1, (size_t)k * ny + j, L.kx[vc_ix(L, nx, j, k)]);
@@ -1874,11 +1940,11 @@ __global__ void k_vc_sweep(VcLevel L, double* phi, const double* bt, int colour,
     const int nx = L.nx, ny = L.ny;
     const int hx = (nx + 1) / 2;                      // cells of one colour per row (at most)
     const size_t total = (size_t)hx * ny * L.nz;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-        const int m = (int)(t % hx);
-        const size_t row = t / hx;
-        const int j = (int)(row % ny), k = (int)(row / ny);
-        const int i = 2 * m + ((j + k + colour) & 1);
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    Walk3 w(t0, stride, hx, ny);   // (m, j, k): the m-th cell of the colour in row (j, k)
+    for (size_t t = t0; t < total; t += stride, w.next()) {
+        const int j = w.j, k = w.k;
+        const int i = 2 * w.i + ((j + k + colour) & 1);
         if (i >= nx) continue;
         double d, sum;
         vc_row(L, phi, i, j, k, d, sum);
@@ -1896,8 +1962,10 @@ __global__ void k_vc_restrict(VcLevel L, const double* phi, const double* bt, do
     if (ctl != nullptr && ctl->done) return;
     const int cnx = L.nx / 2, cny = L.ny / 2, cnz = L.nz / 2;
     const size_t nc = (size_t)cnx * cny * cnz;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nc; t += (size_t)gridDim.x * blockDim.x) {
-        const int I = (int)(t % cnx), J = (int)((t / cnx) % cny), K = (int)(t / ((size_t)cnx * cny));
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    Walk3 w(t0, stride, cnx, cny);
+    for (size_t t = t0; t < nc; t += stride, w.next()) {
+        const int I = w.i, J = w.j, K = w.k;
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -1918,8 +1986,10 @@ __global__ void k_vc_prolong(double* phi, const double* ec, int nx, int ny, int 
     if (ctl != nullptr && ctl->done) return;
     const int cnx = nx / 2, cny = ny / 2;
     const size_t n = (size_t)nx * ny * nz;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+    const size_t c0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    Walk3 w(c0, stride, nx, ny);
+    for (size_t c = c0; c < n; c += stride, w.next()) {
+        const int i = w.i, j = w.j, k = w.k;
         phi[c] += omega * ec[((size_t)(k >> 1) * cny + (j >> 1)) * cnx + (i >> 1)];
     }
 }
@@ -1935,16 +2005,17 @@ __global__ __launch_bounds__(kVcNormThreads) void k_vc_norm(VcLevel L, const dou
     const int nx = L.nx, ny = L.ny;
     const size_t n = (size_t)nx * ny * L.nz;
     double r2 = 0.0, b2 = 0.0;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+    const size_t c0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    Walk3 w(c0, stride, nx, ny);
+    for (size_t c = c0; c < n; c += stride, w.next()) {
         double d, sum;
-        vc_row(L, phi, i, j, k, d, sum);
+        vc_row(L, phi, w.i, w.j, w.k, d, sum);
         const double r = bt[c] - (d * phi[c] - sum);
         r2 += r * r;
         b2 += bt[c] * bt[c];
         if (r_out != nullptr) r_out[c] = r * rscale;
     }
-    finish_norm<kVcNormThreads>(r2, b2, partials, ctl, fin, cycle, (int)gridDim.x, (int)blockIdx.x);
+    store_partials<kVcNormThreads>(r2, b2, partials, (int)blockIdx.x);
 }
 
 // coarsest level: conjugate gradients by one workgroup (Sec. 5.3) on the
