@@ -110,8 +110,8 @@ void ccmg_default_options(ccmg_options* opt);
  * Errors: E_ARG (null out/bc, h <= 0, bad kinds or options, an unpaired
  * periodic face, FP32-IR with variable permittivity or a periodic axis),
  * E_DIMS (a dim not divisible by 2^(levels-1), coarsest grid over
- * CCMG_MAX_COARSE_CELLS cells), E_SINGULAR (no Dirichlet face: every face
- * Neumann or periodic). */
+ * CCMG_MAX_COARSE_CELLS cells, an x-y plane of 2 GiB or more in FP64),
+ * E_SINGULAR (no Dirichlet face: every face Neumann or periodic). */
 int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_face bc[6],
                 const ccmg_options* opt, void* hip_stream);
 

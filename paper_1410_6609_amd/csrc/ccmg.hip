@@ -1065,6 +1065,9 @@ int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_
         return fail(nullptr, CCMG_E_DIMS, "coarsest grid has %zu cells (max %d): use more levels", ncoarse,
                     CCMG_MAX_COARSE_CELLS);
     if ((size_t)nx * ny * nz > (size_t)1 << 34) return fail(nullptr, CCMG_E_DIMS, "grid too large");
+    // the smoother addresses one z-plane per buffer descriptor (32-bit byte offsets)
+    if ((size_t)nx * ny * sizeof(double) >= (size_t)1 << 31)
+        return fail(nullptr, CCMG_E_DIMS, "an x-y plane of %dx%d cells reaches 2 GiB", nx, ny);
 
     ccmg_solver* s = new ccmg_solver();
     s->nx = nx; s->ny = ny; s->nz = nz; s->h = h;

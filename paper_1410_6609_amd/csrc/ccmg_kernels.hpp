@@ -227,6 +227,71 @@ __device__ __forceinline__ void store2(T* p, T a, T b)
     *reinterpret_cast<typename Vec2<T>::type*>(p) = v;
 }
 
+// Raw buffer accesses (gfx9 buffer descriptor, no stride): an access at a
+// byte offset at or beyond the descriptor's size reads 0 and a store there is
+// dropped by the hardware's range check.  The smoother pass addresses one
+// plane per descriptor and gives lanes that must not access (outside the
+// domain or the tile) the offset kOob, so its loads and stores need neither a
+// branch nor zeroed destination registers.  A plane must stay below 2 GiB.
+constexpr unsigned kOob = 0x80000000u;
+constexpr int kBufWord3 = 0x00020000;   // gfx9: 32-bit data format, the rest zero
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, size_t plane_bytes, int t, bool in)
+{
+    const char* p = static_cast<const char*>(base) + (in ? (size_t)t * plane_bytes : 0);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), (short)0, in ? (int)plane_bytes : 0, kBufWord3);
+}
+__device__ __forceinline__ void bload2(__amdgpu_buffer_rsrc_t r, unsigned off, double& a, double& b)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    a = __hiloint2double((int)v[1], (int)v[0]);
+    b = __hiloint2double((int)v[3], (int)v[2]);
+}
+__device__ __forceinline__ void bload2(__amdgpu_buffer_rsrc_t r, unsigned off, float& a, float& b)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    a = __uint_as_float(v[0]);
+    b = __uint_as_float(v[1]);
+}
+__device__ __forceinline__ void bload1(__amdgpu_buffer_rsrc_t r, unsigned off, double& a)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    a = __hiloint2double((int)v[1], (int)v[0]);
+}
+__device__ __forceinline__ void bload1(__amdgpu_buffer_rsrc_t r, unsigned off, float& a)
+{
+    a = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, unsigned off, double a, double b)
+{
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    u4 v;
+    v[0] = (unsigned)__double2loint(a);
+    v[1] = (unsigned)__double2hiint(a);
+    v[2] = (unsigned)__double2loint(b);
+    v[3] = (unsigned)__double2hiint(b);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, unsigned off, float a, float b)
+{
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    u2 v;
+    v[0] = __float_as_uint(a);
+    v[1] = __float_as_uint(b);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore1(__amdgpu_buffer_rsrc_t r, unsigned off, double a)
+{
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    u2 v;
+    v[0] = (unsigned)__double2loint(a);
+    v[1] = (unsigned)__double2hiint(a);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore1(__amdgpu_buffer_rsrc_t r, unsigned off, float a)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(a), r, (int)off, 0, 0);
+}
+
 constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 constexpr int lcm_c(int a, int b) { return a / gcd_c(a, b) * b; }
 
@@ -302,12 +367,28 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
 
     if (P.ctl != nullptr && P.ctl->done) return;
 
-    // strip-edge exchange: [input of stage j+1][step parity][strip][edge row][pair]
-    __shared__ T edge1[Sh::E1][2][NSTRIP][2][32];
-    // both cells of the edge rows, input of the residual stage
-    __shared__ T edge2[RES != RES_NONE ? 2 : 1][NSTRIP][2][32][2];
-    // restriction across strips (odd first row): row-0 pair sums, by step parity
-    __shared__ T rq[Sh::XSTRIP_RESTRICT ? 2 : 1][NSTRIP][32];
+    // strip-edge exchange: [input of stage j+1][step parity][strip + 1][edge row][pair];
+    // slots 0 and NSTRIP + 1 are zero pads, so that the first and the last strip
+    // read their missing neighbour rows unconditionally (no per-lane branch)
+    __shared__ T edge1[Sh::E1][2][NSTRIP + 2][2][32];
+    // both cells of the edge rows, input of the residual stage (same padding)
+    __shared__ T edge2[RES != RES_NONE ? 2 : 1][NSTRIP + 2][2][32][2];
+    // restriction across strips (odd first row): row-0 pair sums, by step parity;
+    // slot NSTRIP is a zero pad
+    __shared__ T rq[Sh::XSTRIP_RESTRICT ? 2 : 1][NSTRIP + 1][32];
+    {
+        constexpr int n1 = Sh::E1 * 2 * 2 * 2 * 32, n2 = (RES != RES_NONE ? 2 : 1) * 2 * 2 * 32 * 2;
+        for (int e = threadIdx.x; e < n1; e += 64 * WY) {
+            const int xp_ = e & 31, row = (e >> 5) & 1, pad = (e >> 6) & 1, rest = e >> 7;   // rest = stage * 2 + parity
+            edge1[rest >> 1][rest & 1][pad ? NSTRIP + 1 : 0][row][xp_] = T(0);
+        }
+        for (int e = threadIdx.x; e < n2; e += 64 * WY) {
+            const int c = e & 1, xp_ = (e >> 1) & 31, row = (e >> 6) & 1, pad = (e >> 7) & 1, par_ = e >> 8;
+            edge2[par_][pad ? NSTRIP + 1 : 0][row][xp_][c] = T(0);
+        }
+        for (int e = threadIdx.x; e < (Sh::XSTRIP_RESTRICT ? 2 : 1) * 32; e += 64 * WY) rq[e >> 5][NSTRIP][e & 31] = T(0);
+        __syncthreads();
+    }
     static_assert(!Sh::XSTRIP_RESTRICT || M == 2, "cross-strip restriction pairs row 1 with the next strip's row 0");
 
     const int nblk = P.tiles_x * P.tiles_y * P.zchunks;
@@ -352,6 +433,22 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     }
     const int cnx = nx >> 1, cny = ny >> 1;
     const size_t plane = (size_t)nx * ny;
+    const size_t planeB = plane * sizeof(T), cplaneB = (size_t)cnx * cny * sizeof(T);
+    // byte offsets in a plane: loads (in the domain), stores (owned by this
+    // tile), parents of the prolongation and coarse cells of the restriction;
+    // kOob where the lane must not access
+    unsigned offL[M], offS[M], offL4[M], offS4[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const unsigned e = (unsigned)((ybase + r) * nx + xl);
+        offL[r] = vrow[r] ? e * (unsigned)sizeof(T) : kOob;
+        offS[r] = (vrow[r] && yin[r] && xin) ? e * (unsigned)sizeof(T) : kOob;
+        offL4[r] = vrow[r] ? e * 4u : kOob;                    // FP32 correction
+        offS4[r] = (vrow[r] && yin[r] && xin) ? e * 4u : kOob;  // FP32 scaled residual
+    }
+    auto coarse_off = [&](int r, bool ok) -> unsigned {
+        return ok ? (unsigned)((((ybase + r) >> 1) * cnx + (xl >> 1)) * (int)sizeof(T)) : kOob;
+    };
 
     T ph[RP][M][2];
     T bb[RB][M][2];
@@ -383,14 +480,14 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     T nph[PD][M][2], nbb[PD][M][2], nex[PD][NE];
     float ncr[PD][M][2];
     // parent values of plane t (zero outside the domain)
+    unsigned offE[NE];
+#pragma unroll
+    for (int r = 0; r < M; r += (YP ? 1 : 2)) offE[YP ? r : r / 2] = coarse_off(r, vrow[r]);
     auto load_parents = [&](int t, T* e) {
         const bool zin = (t >= 0) && (t < nz);
+        const auto re = plane_rsrc(P.ec, cplaneB, t >> 1, zin);
 #pragma unroll
-        for (int r = 0; r < M; r += (YP ? 1 : 2)) {
-            T v = T(0);
-            if (zin && vrow[r]) v = P.ec[((size_t)(t >> 1) * cny + ((ybase + r) >> 1)) * cnx + (xl >> 1)];
-            e[YP ? r : r / 2] = v;
-        }
+        for (int i = 0; i < NE; ++i) bload1(re, offE[i], e[i]);
     };
     // The two planes 2k, 2k+1 share their parent plane: an odd plane reuses
     // the parents of the even plane below it (kept in elast), so only even
@@ -400,19 +497,15 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     for (int i = 0; i < NE; ++i) elast[i] = T(0);
     auto load_plane = [&](int t, int k, auto oddt) {
         const bool zin = (t >= 0) && (t < nz);
+        const auto rb = plane_rsrc(P.b, planeB, t, zin);
+        const auto rp = plane_rsrc(P.phi_in, planeB, t, zin && LOAD != LOAD_ZERO);
+        const auto rc = plane_rsrc(P.corr, plane * sizeof(float), t, zin && LOAD == LOAD_CORR);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
-            T v0 = T(0), v1 = T(0), b0 = T(0), b1 = T(0);
-            float c0 = 0.f, c1 = 0.f;
-            if (zin && vrow[r]) {
-                const size_t idx = (size_t)t * plane + (size_t)(ybase + r) * nx + xl;
-                load2(P.b + idx, b0, b1);
-                if constexpr (LOAD != LOAD_ZERO) load2(P.phi_in + idx, v0, v1);
-                if constexpr (LOAD == LOAD_CORR) load2(P.corr + idx, c0, c1);
-            }
-            nph[k][r][0] = v0; nph[k][r][1] = v1;
-            nbb[k][r][0] = b0; nbb[k][r][1] = b1;
-            if constexpr (LOAD == LOAD_CORR) { ncr[k][r][0] = c0; ncr[k][r][1] = c1; }
+            bload2(rb, offL[r], nbb[k][r][0], nbb[k][r][1]);
+            if constexpr (LOAD != LOAD_ZERO) bload2(rp, offL[r], nph[k][r][0], nph[k][r][1]);
+            else { nph[k][r][0] = T(0); nph[k][r][1] = T(0); }
+            if constexpr (LOAD == LOAD_CORR) bload2(rc, offL4[r], ncr[k][r][0], ncr[k][r][1]);
         }
         if constexpr (LOAD == LOAD_PROLONG && !decltype(oddt)::value) load_parents(t, nex[k]);
     };
@@ -465,13 +558,13 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     const int ppar = (S + q) & 1;
                     if constexpr (SPHI > 0) {
                         const int o0 = (1 + 0 + ppar + YP) & 1, o1 = (1 + (M - 1) + ppar + YP) & 1;
-                        edge1[0][par][strip][0][xp] = ph[s0][0][o0];
-                        edge1[0][par][strip][1][xp] = ph[s0][M - 1][o1];
+                        edge1[0][par][strip + 1][0][xp] = ph[s0][0][o0];
+                        edge1[0][par][strip + 1][1][xp] = ph[s0][M - 1][o1];
                     } else if constexpr (RES != RES_NONE) {
-                        edge2[par][strip][0][xp][0] = ph[s0][0][0];
-                        edge2[par][strip][0][xp][1] = ph[s0][0][1];
-                        edge2[par][strip][1][xp][0] = ph[s0][M - 1][0];
-                        edge2[par][strip][1][xp][1] = ph[s0][M - 1][1];
+                        edge2[par][strip + 1][0][xp][0] = ph[s0][0][0];
+                        edge2[par][strip + 1][0][xp][1] = ph[s0][0][1];
+                        edge2[par][strip + 1][1][xp][0] = ph[s0][M - 1][0];
+                        edge2[par][strip + 1][1][xp][1] = ph[s0][M - 1][1];
                     }
                 }
                 // ---- all strip-edge inputs of this step were written before the last
@@ -480,15 +573,15 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
 #pragma unroll
                 for (int s = 1; s <= SPHI; ++s) {
                     const T* ein = &edge1[s - 1][par ^ 1][0][0][0];
-                    e_lo[s - 1] = strip > 0 ? ein[((strip - 1) * 2 + 1) * 32 + xp] : T(0);
-                    e_hi[s - 1] = strip < NSTRIP - 1 ? ein[((strip + 1) * 2 + 0) * 32 + xp] : T(0);
+                    e_lo[s - 1] = ein[(strip * 2 + 1) * 32 + xp];          // row 1 of strip - 1 (or the pad)
+                    e_hi[s - 1] = ein[((strip + 2) * 2 + 0) * 32 + xp];    // row 0 of strip + 1 (or the pad)
                 }
                 T e2lo[2], e2hi[2];
                 if constexpr (RES != RES_NONE) {
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
-                        e2lo[c] = strip > 0 ? edge2[par ^ 1][strip - 1][1][xp][c] : T(0);
-                        e2hi[c] = strip < NSTRIP - 1 ? edge2[par ^ 1][strip + 1][0][xp][c] : T(0);
+                        e2lo[c] = edge2[par ^ 1][strip][1][xp][c];
+                        e2hi[c] = edge2[par ^ 1][strip + 2][0][xp][c];
                     }
                 }
                 // ---- stages 1..SPHI: colour half-sweeps, red ((x+y+z) even) first
@@ -543,25 +636,23 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     __builtin_amdgcn_sched_barrier(0);
                     if (s < SPHI) {
                         const int o0 = (cs + 0 + ppar + YP) & 1, o1 = (cs + (M - 1) + ppar + YP) & 1;
-                        edge1[s][par][strip][0][xp] = ph[sc][0][o0];
-                        edge1[s][par][strip][1][xp] = ph[sc][M - 1][o1];
+                        edge1[s][par][strip + 1][0][xp] = ph[sc][0][o0];
+                        edge1[s][par][strip + 1][1][xp] = ph[sc][M - 1][o1];
                     } else if (RES != RES_NONE) {
-                        edge2[par][strip][0][xp][0] = ph[sc][0][0];
-                        edge2[par][strip][0][xp][1] = ph[sc][0][1];
-                        edge2[par][strip][1][xp][0] = ph[sc][M - 1][0];
-                        edge2[par][strip][1][xp][1] = ph[sc][M - 1][1];
+                        edge2[par][strip + 1][0][xp][0] = ph[sc][0][0];
+                        edge2[par][strip + 1][0][xp][1] = ph[sc][0][1];
+                        edge2[par][strip + 1][1][xp][0] = ph[sc][M - 1][0];
+                        edge2[par][strip + 1][1][xp][1] = ph[sc][M - 1][1];
                     }
                 }
                 // ---- output of the smoothed plane t - SPHI
                 if (P.phi_out != nullptr) {
                     const int po = t - SPHI;
-                    if (po >= z0 && po < z1 && xin) {
+                    if (po >= z0 && po < z1) {
                         const int so = (q - SPHI + 2 * U) % RP;
+                        const auto rs = plane_rsrc(P.phi_out, planeB, po, true);
 #pragma unroll
-                        for (int r = 0; r < M; ++r)
-                            if (vrow[r] && yin[r])
-                                store2(P.phi_out + (size_t)po * plane + (size_t)(ybase + r) * nx + xl, ph[so][r][0],
-                                       ph[so][r][1]);
+                        for (int r = 0; r < M; ++r) bstore2(rs, offS[r], ph[so][r][0], ph[so][r][1]);
                     }
                 }
                 // ---- restriction across strips of the plane whose residual the
@@ -569,13 +660,13 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                 // y + 1 (the next strip's row 0), planes paired in z as above
                 if constexpr (Sh::XSTRIP_RESTRICT) if (t - 1 - S >= z0 && t - 1 - S < z1) {
                     const int pp = t - 1 - S;
-                    const T q0n = strip < NSTRIP - 1 ? rq[par ^ 1][strip + 1][xp] : T(0);
+                    const T q0n = rq[par ^ 1][strip + 1][xp];             // the pad after the last strip
                     const T s4 = q1p + q0n;
                     if ((pp & 1) == 0) {
                         racc[0] = s4;
-                    } else if (xin && vrow[1] && yin[1]) {
-                        P.bc_out[((size_t)(pp >> 1) * cny + ((ybase + 1) >> 1)) * cnx + (xl >> 1)] =
-                            T(0.25) * (racc[0] + s4);
+                    } else {
+                        const auto rr = plane_rsrc(P.bc_out, cplaneB, pp >> 1, true);
+                        bstore1(rr, coarse_off(1, xin && vrow[1] && yin[1]), T(0.25) * (racc[0] + s4));
                     }
                 }
                 // ---- residual stage at plane t - S (both cells of every pair)
@@ -613,15 +704,15 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                         q1p = res[1][0] + res[1][1];
                     } else if constexpr (RES == RES_RESTRICT) {
                         // children: the pair (x), rows r, r+1 (y), planes p, p+1 (z)
-                        const bool writer = pok && xin;
+                        // p lies in [z0, z1) here
 #pragma unroll
                         for (int r = 0; r < M; r += 2) {
                             const T s4 = (res[r][0] + res[r][1]) + (res[r + 1][0] + res[r + 1][1]);
                             if ((p & 1) == 0) {
                                 racc[r / 2] = s4;
-                            } else if (writer && vrow[r] && yin[r]) {
-                                P.bc_out[((size_t)(p >> 1) * cny + ((ybase + r) >> 1)) * cnx + (xl >> 1)] =
-                                    T(0.25) * (racc[r / 2] + s4);
+                            } else {
+                                const auto rr = plane_rsrc(P.bc_out, cplaneB, p >> 1, true);
+                                bstore1(rr, coarse_off(r, xin && vrow[r] && yin[r]), T(0.25) * (racc[r / 2] + s4));
                             }
                         }
                     } else {
