@@ -341,13 +341,13 @@ struct PassShape {
     static constexpr int RB = S >= 4 ? RP : S + 1;                   // b ring planes
     // planes in flight: the five-stage passes have no registers to spare for a second one
     static constexpr int PD = CCMG_PREFETCH;
-    // The branch-free update (out-of-domain cells have 1/d = 0) issues fewer
-    // instructions, but in the five-stage passes that also load phi the
-    // compiler then runs out of registers; those keep the masked update.
     static constexpr int U = lcm_c(lcm_c(lcm_c(RP, RB), 2), PD);   // unrolled steps
     static constexpr int NT = 64 * WY;
     static constexpr int E1 = SPHI > 0 ? SPHI : 1;                   // single-value edge stages
-    static constexpr bool MASKED_UPDATE = sizeof(T) == 8 && S >= 5 && LOAD != LOAD_ZERO;
+    // FP64 stages skip planes outside the domain (loaded as zeros, they stay
+    // zero); the FP32 passes, at 16 waves per block and 128 registers, keep
+    // updating them with a zeroing select instead, which spills nothing there
+    static constexpr bool SKIP_OUTSIDE = sizeof(T) == 8;
 };
 
 #ifndef CCMG_PASS_WAVES_PER_EU
@@ -594,15 +594,17 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     const int sb = (q - s + 2 * U) % RB;
                     const int cs = (s + 1) & 1;
                     const int ppar = (S + q - s) & 1;
-                    const bool pin = (p >= 0) && (p < nz);
                     int dz = 0;
                     if (p == 0) dz += P.sh[4];
                     if (p == nz - 1) dz += P.sh[5];
                     // Stage s is needed on planes [z0 - (S - s), z1 + (S - s)); outside, its
                     // values are read only by later stages that are skipped as well
                     // (the needed ranges nest), so the halo steps at the chunk ends run
-                    // only the stages that matter.
+                    // only the stages that matter.  Planes outside the domain are skipped
+                    // too (see SKIP_OUTSIDE): they were loaded as zeros and must stay zero.
                     if (p < z0 - (S - s) || p >= z1 + (S - s)) continue;
+                    const bool pin = (p >= 0) && (p < nz);
+                    if (Sh::SKIP_OUTSIDE && !pin) continue;
                     const T elo = e_lo[s - 1];
                     const T ehi = e_hi[s - 1];
                     // 1/diagonal of the updated cell of each row; planes at a z face
@@ -627,9 +629,9 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                         const T ym = r > 0 ? ph[sc][r - 1][o] : elo;
                         const T yp = r < M - 1 ? ph[sc][r + 1][o] : ehi;
                         const T sum = ((((xm + xq) + ym) + yp) + ph[sm][r][o]) + ph[sp][r][o];
-                        // cells outside the domain have inv = 0, planes outside it stay zero
+                        // cells outside the domain have 1/d = 0: they stay zero
                         const T nv = (bb[sb][r][o] + sum) * invz[r];
-                        if constexpr (Sh::MASKED_UPDATE) ph[sc][r][o] = (pin && vrow[r]) ? nv : ph[sc][r][o];
+                        if constexpr (Sh::SKIP_OUTSIDE) ph[sc][r][o] = nv;
                         else ph[sc][r][o] = pin ? nv : T(0);
                     }
                     // keep the stages apart in the schedule (bounds register live ranges)
