@@ -2111,6 +2111,234 @@ __global__ __launch_bounds__(kVcNormThreads) void k_vc_norm(VcLevel L, const dou
     store_partials<kVcNormThreads>(r2, b2, partials, (int)blockIdx.x);
 }
 
+// One red-black Gauss-Seidel sweep on the stored stencil in a single pass
+// (variable permittivity without periodic axes).  The z-marching scheme of
+// k_pass with two stages, red on plane t-1 and black on plane t-2: a lane
+// holds an x-pair, and the face coefficients of its rows travel in register
+// rings beside phi and b-tilde, so a sweep reads phi, b-tilde and the three
+// face arrays once instead of once per colour.  The arithmetic is that of
+// k_vc_sweep: d = the in-domain faces' k plus 2k per Dirichlet boundary face
+// (face weights 1, 2 or 0, exact), the neighbour sum, both in the order x-,
+// x+, y-, y+, z-, z+, and phi = (b-tilde + sum) / d.
+struct VcPassParams {
+    VcLevel L;
+    const double* phi_in;
+    double* phi_out;
+    const double* b;
+    const Ctl* ctl;
+    int zc, tiles_x, tiles_y, zchunks;
+};
+constexpr int kVcPassWaves = 8;
+constexpr int kVcPassRows = 2;
+constexpr int kVcPassTX = 64 - 2 * 2;                                // x halo 2 (two stages)
+constexpr int kVcPassTY = 2 * kVcPassWaves * kVcPassRows - 2 * 2;   // y halo 2
+
+__global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_pass(VcPassParams P)
+{
+    using T = double;
+    constexpr int M = kVcPassRows, WY = kVcPassWaves, S = 2, H = 2, HY = 2;
+    constexpr int NSTRIP = 2 * WY, TX = kVcPassTX, TY = kVcPassTY;
+    constexpr int RP = 4, RF = 3, U = 12;   // ring lengths (b-tilde and faces share RF); U = lcm(RP, RF, 2)
+    if (P.ctl != nullptr && P.ctl->done) return;
+
+    // strip-edge exchange as in k_pass: [stage input][step parity][strip + 1][edge row][pair]
+    __shared__ T edge1[S][2][NSTRIP + 2][2][32];
+    for (int e = threadIdx.x; e < S * 2 * 2 * 2 * 32; e += 64 * WY) {
+        const int xp_ = e & 31, row = (e >> 5) & 1, pad = (e >> 6) & 1, rest = e >> 7;
+        edge1[rest >> 1][rest & 1][pad ? NSTRIP + 1 : 0][row][xp_] = T(0);
+    }
+    __syncthreads();
+
+    const VcLevel& L = P.L;
+    const int nblk = P.tiles_x * P.tiles_y * P.zchunks;
+    const int blk = xcd_block_id(nblk);
+    const int bx = blk % P.tiles_x;
+    const int by = (blk / P.tiles_x) % P.tiles_y;
+    const int bz = blk / (P.tiles_x * P.tiles_y);
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int xp = lane & 31;
+    const int strip = 2 * w + (lane >> 5);
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int xl = bx * TX - H + 2 * xp;
+    const int ybase = by * TY - HY + strip * M;   // even
+    const int z0 = bz * P.zc;
+    const int z1 = min(nz, z0 + P.zc);
+    const bool vx = (xl >= 0) && (xl < nx);
+    const bool xin = (xp >= H / 2) && (xp < H / 2 + TX / 2);
+
+    auto wb = [&](int f) { return L.dir[f] ? T(2) : T(0); };   // boundary face weight
+    bool vrow[M], yin[M];
+    // face weights of the in-domain cells: x and y of the pair and of row 0 are
+    // even and the dims are even, so only the x- face of cell 0, the x+ face of
+    // cell 1, the y- face of row 0 and the y+ face of row 1 can lie on the
+    // boundary; every other weight is 1
+    const T wx0 = xl == 0 ? wb(0) : T(1), wx1 = xl + 1 == nx - 1 ? wb(1) : T(1);
+    const T wy0 = ybase == 0 ? wb(2) : T(1), wy1 = ybase + 1 == ny - 1 ? wb(3) : T(1);
+    static_assert(M == 2, "the boundary weights assume two rows per thread");
+    const size_t planeP = (size_t)nx * ny * sizeof(T);         // phi, b-tilde, one z-face plane
+    const size_t planeX = (size_t)(nx + 1) * ny * sizeof(T);   // x faces of one plane
+    const size_t planeY = (size_t)nx * (ny + 1) * sizeof(T);   // y faces of one plane
+    unsigned offP[M], offS[M], offX[M], offX1[M], offY[M + 1];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const int y = ybase + r;
+        vrow[r] = vx && (y >= 0) && (y < ny);
+        const int ry = strip * M + r;
+        yin[r] = (ry >= HY) && (ry < HY + TY);
+        offP[r] = vrow[r] ? (unsigned)((y * nx + xl) * (int)sizeof(T)) : kOob;
+        offS[r] = (vrow[r] && yin[r] && xin) ? offP[r] : kOob;
+        // x faces xl and xl + 1, also for the lane just beyond the domain's last
+        // cell (xl = nx), whose face xl is the domain's x+ boundary face
+        const bool vf = (xl >= 0) && (xl <= nx) && (y >= 0) && (y < ny);
+        offX[r] = vf ? (unsigned)((y * (nx + 1) + xl) * (int)sizeof(T)) : kOob;
+        offX1[r] = (vf && xl + 1 <= nx) ? offX[r] + (unsigned)sizeof(T) : kOob;
+    }
+#pragma unroll
+    for (int r = 0; r <= M; ++r) {   // y faces below rows 0..M-1 and above row M-1
+        const int y = ybase + r;
+        offY[r] = (vx && y >= 0 && y <= ny) ? (unsigned)((y * nx + xl) * (int)sizeof(T)) : kOob;
+    }
+
+    // rings: phi (planes t-3..t), b-tilde and faces (planes t-2..t); per row the
+    // x faces xl, xl+1 (face xl+2 from the next lane), the y faces below the
+    // rows and above the last, the z faces below the plane
+    T ph[RP][M][2], bb[RF][M][2], fx[RF][M][2], fy[RF][M + 1][2], fz[RF][M][2];
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+#pragma unroll
+        for (int r = 0; r < M; ++r) ph[q][r][0] = ph[q][r][1] = T(0);
+    // phi and the z faces of plane t are read in the step in which the plane
+    // enters (stage 1 of that step needs them as plane t-1's upper neighbours):
+    // they are requested one step ahead into nph / nfz.  b-tilde and the x and
+    // y faces are first read one step later: they are loaded straight into
+    // their ring slot at the end of the previous step, after stage 2 has
+    // finished with the plane that slot held.
+    T nph[M][2], nfz[M][2];
+    auto load_early = [&](int t) {
+        const bool zin = (t >= 0) && (t < nz);
+        const bool zinf = (t >= 0) && (t <= nz);   // z faces: nz + 1 planes
+        const auto rp = plane_rsrc(P.phi_in, planeP, t, zin);
+        const auto rz = plane_rsrc(L.kz, planeP, t, zinf);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            bload2(rp, offP[r], nph[r][0], nph[r][1]);
+            bload2(rz, offP[r], nfz[r][0], nfz[r][1]);
+        }
+    };
+    auto load_late = [&](int t, int slot) {
+        const bool zin = (t >= 0) && (t < nz);
+        const auto rb = plane_rsrc(P.b, planeP, t, zin);
+        const auto rx = plane_rsrc(L.kx, planeX, t, zin);
+        const auto ry = plane_rsrc(L.ky, planeY, t, zin);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            bload2(rb, offP[r], bb[slot][r][0], bb[slot][r][1]);
+            bload1(rx, offX[r], fx[slot][r][0]);
+            bload1(rx, offX1[r], fx[slot][r][1]);
+        }
+#pragma unroll
+        for (int r = 0; r <= M; ++r) bload2(ry, offY[r], fy[slot][r][0], fy[slot][r][1]);
+    };
+
+    const int tbeg = z0 - S, tend = z1 + S;   // tbeg even (z0 even, S = 2)
+    load_early(tbeg);
+    load_late(tbeg, 0);
+    for (int tb = tbeg; tb < tend; tb += U) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int t = tb + q;
+            if (t < tend) {
+                const int par = t & 1;
+                // ---- stage 0: plane t enters the rings; plane t + 1 is requested
+                {
+                    const int s0 = q % RP, sf0 = q % RF;
+#pragma unroll
+                    for (int r = 0; r < M; ++r) {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            ph[s0][r][c] = nph[r][c];
+                            fz[sf0][r][c] = nfz[r][c];
+                        }
+                    }
+                    if (t + 1 < tend) load_early(t + 1);
+                    const int ppar = q & 1;   // parity of plane t
+                    // black cells of the edge rows: the neighbours the red stage needs
+                    edge1[0][par][strip + 1][0][xp] = ph[s0][0][(1 + 0 + ppar) & 1];
+                    edge1[0][par][strip + 1][1][xp] = ph[s0][M - 1][(1 + (M - 1) + ppar) & 1];
+                }
+                T e_lo[S], e_hi[S];
+#pragma unroll
+                for (int s = 1; s <= S; ++s) {
+                    const T* ein = &edge1[s - 1][par ^ 1][0][0][0];
+                    e_lo[s - 1] = ein[(strip * 2 + 1) * 32 + xp];
+                    e_hi[s - 1] = ein[((strip + 2) * 2 + 0) * 32 + xp];
+                }
+                // ---- stages 1 (red) and 2 (black)
+#pragma unroll
+                for (int s = 1; s <= S; ++s) {
+                    const int p = t - s;
+                    const int sc = (q - s + 2 * U) % RP;
+                    const int sm = (q - s - 1 + 2 * U) % RP;
+                    const int sp = (q - s + 1 + 2 * U) % RP;
+                    const int sf = (q - s + 2 * U) % RF;
+                    const int sfp = (q - s + 1 + 2 * U) % RF;   // faces of plane p + 1 (its lower z face)
+                    const int cs = (s + 1) & 1;
+                    const int ppar = (q - s) & 1;
+                    if (p < z0 - (S - s) || p >= z1 + (S - s)) continue;
+                    if (p < 0 || p >= nz) continue;   // planes outside the domain stay zero
+                    const T wzm = p == 0 ? wb(4) : T(1);
+                    const T wzp = p == nz - 1 ? wb(5) : T(1);
+#pragma unroll
+                    for (int r = 0; r < M; ++r) {
+                        const int o = (cs + r + ppar) & 1;
+                        T xm, xq;
+                        if (o == 0) { xm = lane_prev(ph[sc][r][1]); xq = ph[sc][r][1]; }
+                        else        { xm = ph[sc][r][0]; xq = lane_next(ph[sc][r][0]); }
+                        const T kxm = fx[sf][r][o], kxp = o == 0 ? fx[sf][r][1] : lane_next(fx[sf][r][0]);
+                        const T ym = r > 0 ? ph[sc][r - 1][o] : e_lo[s - 1];
+                        const T yq = r < M - 1 ? ph[sc][r + 1][o] : e_hi[s - 1];
+                        const T kym = fy[sf][r][o], kyp = fy[sf][r + 1][o];
+                        const T kzm = fz[sf][r][o], kzp = fz[sfp][r][o];
+                        T dd = (o == 0 ? wx0 : T(1)) * kxm;
+                        dd += (o == 1 ? wx1 : T(1)) * kxp;
+                        dd += (r == 0 ? wy0 : T(1)) * kym;
+                        dd += (r == 1 ? wy1 : T(1)) * kyp;
+                        dd += wzm * kzm;
+                        dd += wzp * kzp;
+                        // neighbours outside the domain are zero: their terms add nothing
+                        T ss = kxm * xm;
+                        ss += kxp * xq;
+                        ss += kym * ym;
+                        ss += kyp * yq;
+                        ss += kzm * ph[sm][r][o];
+                        ss += kzp * ph[sp][r][o];
+                        const T nv = (bb[sf][r][o] + ss) / dd;
+                        ph[sc][r][o] = vrow[r] ? nv : T(0);   // cells outside the domain have d = 0
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (s < S) {
+                        edge1[s][par][strip + 1][0][xp] = ph[sc][0][(cs + 0 + ppar) & 1];
+                        edge1[s][par][strip + 1][1][xp] = ph[sc][M - 1][(cs + (M - 1) + ppar) & 1];
+                    }
+                }
+                // ---- output of the swept plane t - 2
+                {
+                    const int po = t - S;
+                    if (po >= z0 && po < z1) {
+                        const int so = (q - S + 2 * U) % RP;
+                        const auto rs = plane_rsrc(P.phi_out, planeP, po, true);
+#pragma unroll
+                        for (int r = 0; r < M; ++r) bstore2(rs, offS[r], ph[so][r][0], ph[so][r][1]);
+                    }
+                }
+                if (t + 1 < tend) load_late(t + 1, (q + 1) % RF);
+                __syncthreads();
+            }
+        }
+    }
+}
+
 // coarsest level: conjugate gradients by one workgroup (Sec. 5.3) on the
 // stored stencil, from x = 0 until ||r|| <= rtol ||b|| or maxit; vectors in LDS
 constexpr int kVcCgThreads = 512;
