@@ -578,8 +578,55 @@ int enqueue_vc_fold(ccmg_solver* s, const double* f, bool homogeneous)
     return CCMG_OK;
 }
 
+// Fused stored-stencil residual pass over level l (no periodic axis):
+// RESTRICT writes the coarse b-tilde and zeroes the coarse phi, otherwise the
+// blocks store their norm partials.  Returns the block count, 0 if the grid
+// needs more partials than the workspace holds (nothing launched).
+template <bool RESTRICT>
+int launch_vc_res(ccmg_solver* s, int l, const double* phi, double* bc_out, double* phic, int fin)
+{
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_vc_res<RESTRICT>),
+                                                         64 * kVcPassWaves, 0) != hipSuccess || nb < 1) {
+            (void)hipGetLastError();
+            nb = 1;
+        }
+        per_cu = nb;
+    }
+    const LevelBuf& B = s->lv[l];
+    const Grid g = pass_grid(B.nx, B.ny, B.nz, kVcPassTX, kVcPassTY, 2, g_num_cus * per_cu);
+    if (!RESTRICT && g.blocks() > s->max_partials) return 0;
+    VcResParams P;
+    std::memset(&P, 0, sizeof P);
+    P.L = vc_level(s, l);
+    P.phi = phi;
+    P.b = B.b;
+    P.bc_out = bc_out;
+    P.phic = phic;
+    P.partials = s->partials;
+    P.ctl = s->ctl;
+    P.fin = fin;
+    P.zc = g.zc;
+    P.tiles_x = g.tiles_x;
+    P.tiles_y = g.tiles_y;
+    P.zchunks = g.zchunks;
+    hipLaunchKernelGGL(k_vc_res<RESTRICT>, dim3(g.blocks()), dim3(64 * kVcPassWaves), 0, s->stream, P);
+    return g.blocks();
+}
+
 int enqueue_vc_norm(ccmg_solver* s, const double* phi, int fin, double* r_out, double rscale, int cycle)
 {
+    if (!s->periodic && r_out == nullptr) {
+        const int nb = launch_vc_res<false>(s, 0, phi, nullptr, nullptr, fin);
+        if (nb > 0) {
+            hipLaunchKernelGGL(k_finish_norm<64 * kVcPassWaves>, dim3(1), dim3(64 * kVcPassWaves), 0, s->stream,
+                               (const double*)s->partials, nb, s->ctl, fin, cycle, fin == FIN_CYCLE ? 1 : 0);
+            LAUNCHCHK(s);
+            return CCMG_OK;
+        }
+    }
     const int g = std::max(1, std::min(vc_grid(s->lv[0].n), s->max_partials));
     hipLaunchKernelGGL(k_vc_norm, dim3(g), dim3(kVcNormThreads), 0, s->stream, vc_level(s, 0), phi,
                        (const double*)s->lv[0].b, r_out, rscale, s->partials, s->ctl, fin, cycle);
@@ -650,10 +697,14 @@ int enqueue_vc_cycle(ccmg_solver* s, double* phi0, int fin_cycle)
     auto home = [&](int l) { return l == 0 ? phi0 : s->lv[l].phi; };
     for (int l = 0; l + 1 < L; ++l) {
         enqueue_vc_smooth(s, l, home(l), s->opt.nu1);
-        const size_t nc = s->lv[l + 1].n;
-        hipLaunchKernelGGL(k_vc_restrict, dim3(vc_grid(nc)), dim3(256), 0, s->stream, vc_level(s, l),
-                           (const double*)home(l), (const double*)s->lv[l].b, s->lv[l + 1].b, home(l + 1),
-                           (const Ctl*)s->ctl);
+        if (!s->periodic) {
+            launch_vc_res<true>(s, l, home(l), s->lv[l + 1].b, home(l + 1), 0);
+        } else {
+            const size_t nc = s->lv[l + 1].n;
+            hipLaunchKernelGGL(k_vc_restrict, dim3(vc_grid(nc)), dim3(256), 0, s->stream, vc_level(s, l),
+                               (const double*)home(l), (const double*)s->lv[l].b, s->lv[l + 1].b, home(l + 1),
+                               (const Ctl*)s->ctl);
+        }
     }
     {
         const VcLevel V = vc_level(s, L - 1);

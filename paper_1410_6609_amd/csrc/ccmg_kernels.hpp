@@ -2339,6 +2339,223 @@ __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_pass(VcPassParams P
     }
 }
 
+// The stored-stencil residual r = b-tilde - (d phi - sum k phi_nb) of every
+// cell in one z-marching pass (same layout, descriptors and strip-edge
+// exchange as k_vc_pass, one stage: the residual of plane t-1 at step t),
+// either restricted (RESTRICT: b-tilde of level l+1 = 1/4 of the sum over the
+// 8 children, the coarse phi set to zero) or reduced to block partials of
+// ||r||^2 and ||b-tilde||^2 for k_finish_norm.
+struct VcResParams {
+    VcLevel L;
+    const double* phi;
+    const double* b;
+    double* bc_out;      // RESTRICT: b-tilde of level l+1
+    double* phic;        // RESTRICT: phi of level l+1 (zeroed)
+    double* partials;    // norm: 2 doubles per block
+    const Ctl* ctl;
+    int fin;             // norm: FIN_CYCLE skips when ctl->done
+    int zc, tiles_x, tiles_y, zchunks;
+};
+
+template <bool RESTRICT>
+__global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_res(VcResParams P)
+{
+    using T = double;
+    constexpr int M = kVcPassRows, WY = kVcPassWaves, S = 1, H = 2, HY = 2;
+    constexpr int NSTRIP = 2 * WY, TX = kVcPassTX, TY = kVcPassTY;
+    constexpr int RP = 4, RF = 2, U = 4;   // phi: planes t-3..t (t-2..t used); b-tilde, faces: t-1, t
+    if (RESTRICT ? (P.ctl != nullptr && P.ctl->done) : (P.fin == FIN_CYCLE && P.ctl->done)) return;
+
+    // both cells of the edge rows of the plane that entered in the previous step
+    __shared__ T edge2[2][NSTRIP + 2][2][32][2];
+    for (int e = threadIdx.x; e < 2 * 2 * 2 * 32 * 2; e += 64 * WY) {
+        const int c = e & 1, xp_ = (e >> 1) & 31, row = (e >> 6) & 1, pad = (e >> 7) & 1, par_ = e >> 8;
+        edge2[par_][pad ? NSTRIP + 1 : 0][row][xp_][c] = T(0);
+    }
+    __syncthreads();
+
+    const VcLevel& L = P.L;
+    const int nblk = P.tiles_x * P.tiles_y * P.zchunks;
+    const int blk = xcd_block_id(nblk);
+    const int bx = blk % P.tiles_x;
+    const int by = (blk / P.tiles_x) % P.tiles_y;
+    const int bz = blk / (P.tiles_x * P.tiles_y);
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int xp = lane & 31;
+    const int strip = 2 * w + (lane >> 5);
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int xl = bx * TX - H + 2 * xp;
+    const int ybase = by * TY - HY + strip * M;   // even
+    const int z0 = bz * P.zc;
+    const int z1 = min(nz, z0 + P.zc);
+    const bool vx = (xl >= 0) && (xl < nx);
+    const bool xin = (xp >= H / 2) && (xp < H / 2 + TX / 2);
+
+    auto wb = [&](int f) { return L.dir[f] ? T(2) : T(0); };
+    const T wx0 = xl == 0 ? wb(0) : T(1), wx1 = xl + 1 == nx - 1 ? wb(1) : T(1);
+    const T wy0 = ybase == 0 ? wb(2) : T(1), wy1 = ybase + 1 == ny - 1 ? wb(3) : T(1);
+    static_assert(M == 2, "the boundary weights and the restriction assume two rows per thread");
+    bool vrow[M], own[M];
+    const size_t planeP = (size_t)nx * ny * sizeof(T);
+    const size_t planeX = (size_t)(nx + 1) * ny * sizeof(T);
+    const size_t planeY = (size_t)nx * (ny + 1) * sizeof(T);
+    unsigned offP[M], offX[M], offX1[M], offY[M + 1];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const int y = ybase + r;
+        vrow[r] = vx && (y >= 0) && (y < ny);
+        const int ry = strip * M + r;
+        own[r] = vrow[r] && xin && (ry >= HY) && (ry < HY + TY);
+        offP[r] = vrow[r] ? (unsigned)((y * nx + xl) * (int)sizeof(T)) : kOob;
+        const bool vf = (xl >= 0) && (xl <= nx) && (y >= 0) && (y < ny);
+        offX[r] = vf ? (unsigned)((y * (nx + 1) + xl) * (int)sizeof(T)) : kOob;
+        offX1[r] = (vf && xl + 1 <= nx) ? offX[r] + (unsigned)sizeof(T) : kOob;
+    }
+#pragma unroll
+    for (int r = 0; r <= M; ++r) {
+        const int y = ybase + r;
+        offY[r] = (vx && y >= 0 && y <= ny) ? (unsigned)((y * nx + xl) * (int)sizeof(T)) : kOob;
+    }
+    // the coarse cell of the pair's rows (0, 1): written by the owning lanes
+    const int cnx = nx >> 1, cny = ny >> 1;
+    const size_t cplane = (size_t)cnx * cny * sizeof(T);
+    const unsigned offC = own[0] ? (unsigned)(((ybase >> 1) * cnx + (xl >> 1)) * (int)sizeof(T)) : kOob;
+
+    T ph[RP][M][2], bb[RF][M][2], fx[RF][M][2], fy[RF][M + 1][2], fz[RF][M][2];
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+#pragma unroll
+        for (int r = 0; r < M; ++r) ph[q][r][0] = ph[q][r][1] = T(0);
+    T nph[M][2], nfz[M][2];
+    auto load_early = [&](int t) {
+        const bool zin = (t >= 0) && (t < nz);
+        const bool zinf = (t >= 0) && (t <= nz);
+        const auto rp = plane_rsrc(P.phi, planeP, t, zin);
+        const auto rz = plane_rsrc(L.kz, planeP, t, zinf);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            bload2(rp, offP[r], nph[r][0], nph[r][1]);
+            bload2(rz, offP[r], nfz[r][0], nfz[r][1]);
+        }
+    };
+    auto load_late = [&](int t, int slot) {
+        const bool zin = (t >= 0) && (t < nz);
+        const auto rb = plane_rsrc(P.b, planeP, t, zin);
+        const auto rx = plane_rsrc(L.kx, planeX, t, zin);
+        const auto ry = plane_rsrc(L.ky, planeY, t, zin);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            bload2(rb, offP[r], bb[slot][r][0], bb[slot][r][1]);
+            bload1(rx, offX[r], fx[slot][r][0]);
+            bload1(rx, offX1[r], fx[slot][r][1]);
+        }
+#pragma unroll
+        for (int r = 0; r <= M; ++r) bload2(ry, offY[r], fy[slot][r][0], fy[slot][r][1]);
+    };
+
+    double acc_r2 = 0.0, acc_b2 = 0.0;
+    T racc = T(0);
+    const int tbeg = z0 - S - 1, tend = z1 + S;   // tbeg even: plane z0 - 1 enters first (the residual needs z0 - 1)
+    load_early(tbeg);
+    load_late(tbeg, 0);
+    for (int tb = tbeg; tb < tend; tb += U) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int t = tb + q;
+            if (t < tend) {
+                const int par = t & 1;
+                {
+                    const int s0 = q % RP, sf0 = q % RF;
+#pragma unroll
+                    for (int r = 0; r < M; ++r) {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            ph[s0][r][c] = nph[r][c];
+                            fz[sf0][r][c] = nfz[r][c];
+                        }
+                    }
+                    if (t + 1 < tend) load_early(t + 1);
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        edge2[par][strip + 1][0][xp][c] = ph[s0][0][c];
+                        edge2[par][strip + 1][1][xp][c] = ph[s0][M - 1][c];
+                    }
+                }
+                // ---- the residual of plane p = t - 1
+                const int p = t - 1;
+                if (p >= z0 && p < z1) {
+                    const int sc = (q - 1 + 2 * U) % RP, sm = (q - 2 + 2 * U) % RP, sp = q % RP;
+                    const int sf = (q - 1 + 2 * U) % RF;
+                    const int szm = sf, szp = q % RF;   // z faces below plane p and below plane p + 1
+                    const T wzm = p == 0 ? wb(4) : T(1);
+                    const T wzp = p == nz - 1 ? wb(5) : T(1);
+                    T elo[2], ehi[2];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        elo[c] = edge2[par ^ 1][strip][1][xp][c];
+                        ehi[c] = edge2[par ^ 1][strip + 2][0][xp][c];
+                    }
+                    T res[M][2];
+#pragma unroll
+                    for (int r = 0; r < M; ++r) {
+                        const T pm = lane_prev(ph[sc][r][1]);
+                        const T pn = lane_next(ph[sc][r][0]);
+                        const T kn = lane_next(fx[sf][r][0]);
+#pragma unroll
+                        for (int o = 0; o < 2; ++o) {
+                            const T xm = o == 0 ? pm : ph[sc][r][0];
+                            const T xq = o == 0 ? ph[sc][r][1] : pn;
+                            const T kxm = fx[sf][r][o], kxp = o == 0 ? fx[sf][r][1] : kn;
+                            const T ym = r > 0 ? ph[sc][r - 1][o] : elo[o];
+                            const T yq = r < M - 1 ? ph[sc][r + 1][o] : ehi[o];
+                            const T kym = fy[sf][r][o], kyp = fy[sf][r + 1][o];
+                            const T kzm = fz[szm][r][o], kzp = fz[szp][r][o];
+                            T dd = (o == 0 ? wx0 : T(1)) * kxm;
+                            dd += (o == 1 ? wx1 : T(1)) * kxp;
+                            dd += (r == 0 ? wy0 : T(1)) * kym;
+                            dd += (r == 1 ? wy1 : T(1)) * kyp;
+                            dd += wzm * kzm;
+                            dd += wzp * kzp;
+                            T ss = kxm * xm;
+                            ss += kxp * xq;
+                            ss += kym * ym;
+                            ss += kyp * yq;
+                            ss += kzm * ph[sm][r][o];
+                            ss += kzp * ph[sp][r][o];
+                            res[r][o] = bb[sf][r][o] - (dd * ph[sc][r][o] - ss);
+                        }
+                    }
+                    if constexpr (RESTRICT) {
+                        // children: the pair (x), rows 0 and 1 (y), planes p and p + 1 (z)
+                        const T s4 = (res[0][0] + res[0][1]) + (res[1][0] + res[1][1]);
+                        if ((p & 1) == 0) {
+                            racc = s4;
+                        } else {
+                            const int pc = p >> 1;
+                            const auto rc = plane_rsrc(P.bc_out, cplane, pc, true);
+                            const auto rz = plane_rsrc(P.phic, cplane, pc, true);
+                            bstore1(rc, offC, T(0.25) * (racc + s4));
+                            bstore1(rz, offC, T(0));
+                        }
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < M; ++r) {
+                            if (own[r]) {
+                                acc_r2 += res[r][0] * res[r][0] + res[r][1] * res[r][1];
+                                acc_b2 += bb[sf][r][0] * bb[sf][r][0] + bb[sf][r][1] * bb[sf][r][1];
+                            }
+                        }
+                    }
+                }
+                if (t + 1 < tend) load_late(t + 1, (q + 1) % RF);
+                __syncthreads();
+            }
+        }
+    }
+    if constexpr (!RESTRICT) store_partials<64 * WY>(acc_r2, acc_b2, P.partials, blk);
+}
+
 // coarsest level: conjugate gradients by one workgroup (Sec. 5.3) on the
 // stored stencil, from x = 0 until ||r|| <= rtol ||b|| or maxit; vectors in LDS
 constexpr int kVcCgThreads = 512;
