@@ -708,9 +708,16 @@ int enqueue_vc_cycle(ccmg_solver* s, double* phi0, int fin_cycle)
     }
     {
         const VcLevel V = vc_level(s, L - 1);
-        const size_t lds = 4 * sizeof(double) * s->lv[L - 1].n;
-        hipLaunchKernelGGL(k_vc_cg, dim3(1), dim3(kVcCgThreads), lds, s->stream, V, (const double*)s->lv[L - 1].b,
-                           home(L - 1), s->opt.cg_rtol, s->cg_maxit, (const Ctl*)s->ctl);
+        if (s->lv[L - 1].n <= (size_t)kVcCgThreads) {
+            hipLaunchKernelGGL(k_vc_cg_cell, dim3(1), dim3(kVcCgThreads), 0, s->stream, V,
+                               (const double*)s->lv[L - 1].b, home(L - 1), s->opt.cg_rtol, s->cg_maxit,
+                               (const Ctl*)s->ctl);
+        } else {
+            const size_t lds = 4 * sizeof(double) * s->lv[L - 1].n;
+            hipLaunchKernelGGL(k_vc_cg, dim3(1), dim3(kVcCgThreads), lds, s->stream, V,
+                               (const double*)s->lv[L - 1].b, home(L - 1), s->opt.cg_rtol, s->cg_maxit,
+                               (const Ctl*)s->ctl);
+        }
     }
     for (int l = L - 2; l >= 0; --l) {
         hipLaunchKernelGGL(k_vc_prolong, dim3(vc_grid(s->lv[l].n)), dim3(256), 0, s->stream, home(l),

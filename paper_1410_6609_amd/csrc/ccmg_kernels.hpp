@@ -2556,9 +2556,96 @@ __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_res(VcResParams P)
     if constexpr (!RESTRICT) store_partials<64 * WY>(acc_r2, acc_b2, P.partials, blk);
 }
 
+constexpr int kVcCgThreads = 512;
+
+// Coarsest-level CG on the stored stencil with one cell per thread (n <=
+// kVcCgThreads, Sec. 5.3): the cell's face coefficients, diagonal and
+// neighbour indices (as vc_row, periodic wrap included) stay in registers and
+// only the residual passes through LDS.  Arranged as cg_one_wave
+// (Chronopoulos and Gear): (r, r) and (r, S r) in one combined reduction per
+// iteration, two workgroup barriers per iteration; x = 0 to ||r|| <= rtol ||b||
+// or maxit.
+__global__ __launch_bounds__(kVcCgThreads) void k_vc_cg_cell(VcLevel L, const double* b, double* x_out, double rtol,
+                                                            int maxit, const Ctl* ctl)
+{
+    if (ctl != nullptr && ctl->done) return;
+    constexpr int NW = kVcCgThreads / 64;
+    __shared__ double rl[kVcCgThreads];
+    __shared__ double red[2][NW];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nx = L.nx, ny = L.ny, nz = L.nz, n = nx * ny * nz;
+    const bool v = tid < n;
+    int i, j, k;
+    split3(v ? tid : 0, SmallDiv(nx), SmallDiv(ny), i, j, k);
+    const int c = tid, sy = nx, sz = nx * ny;
+    const int wx = nx - 1, wy = (ny - 1) * sy, wz = (nz - 1) * sz;
+    double kf[6];
+    int nb[6];
+    double d = 0.0;
+    // face f with coefficient kk: an in-domain (or periodic) neighbour at index m,
+    // or a boundary face (no term; 2 kk on the diagonal when Dirichlet)
+    auto face = [&](int f, double kk, bool inside, bool wrap, int m_in, int m_wrap) {
+        if (inside) { d += kk; kf[f] = kk; nb[f] = m_in; }
+        else if (wrap) { d += kk; kf[f] = kk; nb[f] = m_wrap; }
+        else { if (L.dir[f]) d += 2.0 * kk; kf[f] = 0.0; nb[f] = c; }
+    };
+    if (v) {
+        face(0, L.kx[vc_ix(L, i, j, k)], i > 0, L.per[0] != 0, c - 1, c + wx);
+        face(1, L.kx[vc_ix(L, i + 1, j, k)], i < nx - 1, L.per[0] != 0, c + 1, c - wx);
+        face(2, L.ky[vc_iy(L, i, j, k)], j > 0, L.per[1] != 0, c - sy, c + wy);
+        face(3, L.ky[vc_iy(L, i, j + 1, k)], j < ny - 1, L.per[1] != 0, c + sy, c - wy);
+        face(4, L.kz[vc_iz(L, i, j, k)], k > 0, L.per[2] != 0, c - sz, c + wz);
+        face(5, L.kz[vc_iz(L, i, j, k + 1)], k < nz - 1, L.per[2] != 0, c + sz, c - wz);
+    } else {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) { kf[f] = 0.0; nb[f] = 0; }
+    }
+    double rv = v ? b[tid] : 0.0, xr = 0.0, pv = 0.0, sv = 0.0;
+    rl[tid] = rv;
+    double gamma_old = 1.0, alpha_old = 1.0, bound = 0.0;
+    int it = 0;
+    while (true) {
+        __syncthreads();   // the residual in LDS is complete
+        double ss = kf[0] * rl[nb[0]];
+        ss += kf[1] * rl[nb[1]];
+        ss += kf[2] * rl[nb[2]];
+        ss += kf[3] * rl[nb[3]];
+        ss += kf[4] * rl[nb[4]];
+        ss += kf[5] * rl[nb[5]];
+        const double wv = v ? d * rv - ss : 0.0;
+        double gamma = rv * rv, delta = rv * wv;
+        gamma = wave_sum(gamma);
+        delta = wave_sum(delta);
+        if (lane == 0) { red[0][w] = gamma; red[1][w] = delta; }
+        __syncthreads();   // every wave's sums are in LDS; every read of rl above is done
+        gamma = 0.0;
+        delta = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) { gamma += red[0][q]; delta += red[1][q]; }
+        // every thread holds the same sums: the exits are uniform
+        if (it == 0) {
+            if (!(gamma > 0.0)) break;
+            bound = rtol * rtol * gamma;
+        } else if (gamma <= bound) {
+            break;
+        }
+        if (it >= maxit) break;
+        const double beta = it == 0 ? 0.0 : gamma / gamma_old;
+        const double alpha = gamma / (delta - beta * gamma / alpha_old);
+        pv = rv + beta * pv;
+        sv = wv + beta * sv;
+        xr += alpha * pv;
+        rv -= alpha * sv;
+        rl[tid] = rv;
+        ++it;
+        gamma_old = gamma;
+        alpha_old = alpha;
+    }
+    if (v) x_out[tid] = xr;
+}
+
 // coarsest level: conjugate gradients by one workgroup (Sec. 5.3) on the
 // stored stencil, from x = 0 until ||r|| <= rtol ||b|| or maxit; vectors in LDS
-constexpr int kVcCgThreads = 512;
 __global__ __launch_bounds__(kVcCgThreads) void k_vc_cg(VcLevel L, const double* b, double* x_out, double rtol,
                                                        int maxit, const Ctl* ctl)
 {
