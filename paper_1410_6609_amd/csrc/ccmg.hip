@@ -648,31 +648,39 @@ void enqueue_vc_sweeps(ccmg_solver* s, int l, double* phi, int sweeps)
 
 // one V(nu1,nu2)-cycle on the variable-permittivity hierarchy; fin_cycle > 0
 // finalises the finest residual norm as that cycle
-// `sweeps` red-black sweeps on level l.  Without a periodic axis each sweep is
-// one fused pass (k_vc_pass) from one buffer into the other, ending in `home`
-// (a copy when the count is odd); a periodic axis takes the colour kernels.
-void enqueue_vc_smooth(ccmg_solver* s, int l, double* home, int sweeps)
+// `sweeps` red-black sweeps on level l, after the prolongation of the coarse
+// correction ec (home += omega * e(parent)) when ec is given.  Without a
+// periodic axis each sweep is one fused pass (k_vc_pass; the first one also
+// applies the prolongation) from one buffer into the other, ending in `home`
+// (a copy when the count is odd); a periodic axis takes the separate
+// prolongation and the colour kernels.
+void enqueue_vc_smooth(ccmg_solver* s, int l, double* home, int sweeps, const double* ec)
 {
+    const LevelBuf& B = s->lv[l];
     if (s->periodic || sweeps <= 0) {
+        if (ec != nullptr)
+            hipLaunchKernelGGL(k_vc_prolong, dim3(vc_grid(B.n)), dim3(256), 0, s->stream, home, ec, B.nx, B.ny, B.nz,
+                               s->opt.omega, (const Ctl*)s->ctl);
         enqueue_vc_sweeps(s, l, home, sweeps);
         return;
     }
     static int per_cu = 0;
     if (per_cu == 0) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_vc_pass),
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_vc_pass<true>),
                                                          64 * kVcPassWaves, 0) != hipSuccess || nb < 1) {
             (void)hipGetLastError();
             nb = 1;
         }
         per_cu = nb;
     }
-    const LevelBuf& B = s->lv[l];
     const Grid g = pass_grid(B.nx, B.ny, B.nz, kVcPassTX, kVcPassTY, 2, g_num_cus * per_cu);
     VcPassParams P;
     std::memset(&P, 0, sizeof P);
     P.L = vc_level(s, l);
     P.b = B.b;
+    P.ec = ec;
+    P.omega = s->opt.omega;
     P.ctl = s->ctl;
     P.zc = g.zc;
     P.tiles_x = g.tiles_x;
@@ -683,7 +691,10 @@ void enqueue_vc_smooth(ccmg_solver* s, int l, double* home, int sweeps)
     for (int k = 0; k < sweeps; ++k) {
         P.phi_in = buf[cur];
         P.phi_out = buf[cur ^ 1];
-        hipLaunchKernelGGL(k_vc_pass, dim3(g.blocks()), dim3(64 * kVcPassWaves), 0, s->stream, P);
+        if (k == 0 && ec != nullptr)
+            hipLaunchKernelGGL(k_vc_pass<true>, dim3(g.blocks()), dim3(64 * kVcPassWaves), 0, s->stream, P);
+        else
+            hipLaunchKernelGGL(k_vc_pass<false>, dim3(g.blocks()), dim3(64 * kVcPassWaves), 0, s->stream, P);
         cur ^= 1;
     }
     if (cur != 0)
@@ -696,7 +707,7 @@ int enqueue_vc_cycle(ccmg_solver* s, double* phi0, int fin_cycle)
     const int L = s->L;
     auto home = [&](int l) { return l == 0 ? phi0 : s->lv[l].phi; };
     for (int l = 0; l + 1 < L; ++l) {
-        enqueue_vc_smooth(s, l, home(l), s->opt.nu1);
+        enqueue_vc_smooth(s, l, home(l), s->opt.nu1, nullptr);
         if (!s->periodic) {
             launch_vc_res<true>(s, l, home(l), s->lv[l + 1].b, home(l + 1), 0);
         } else {
@@ -719,12 +730,7 @@ int enqueue_vc_cycle(ccmg_solver* s, double* phi0, int fin_cycle)
                                (const Ctl*)s->ctl);
         }
     }
-    for (int l = L - 2; l >= 0; --l) {
-        hipLaunchKernelGGL(k_vc_prolong, dim3(vc_grid(s->lv[l].n)), dim3(256), 0, s->stream, home(l),
-                           (const double*)home(l + 1), s->lv[l].nx, s->lv[l].ny, s->lv[l].nz, s->opt.omega,
-                           (const Ctl*)s->ctl);
-        enqueue_vc_smooth(s, l, home(l), s->opt.nu2);
-    }
+    for (int l = L - 2; l >= 0; --l) enqueue_vc_smooth(s, l, home(l), s->opt.nu2, home(l + 1));
     LAUNCHCHK(s);
     if (fin_cycle > 0) return enqueue_vc_norm(s, phi0, FIN_CYCLE, nullptr, 0.0, fin_cycle);
     return CCMG_OK;

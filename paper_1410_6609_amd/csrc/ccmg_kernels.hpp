@@ -2125,6 +2125,8 @@ struct VcPassParams {
     const double* phi_in;
     double* phi_out;
     const double* b;
+    const double* ec;    // PROLONG: correction of level l+1, added as omega * e(parent) on loading
+    double omega;
     const Ctl* ctl;
     int zc, tiles_x, tiles_y, zchunks;
 };
@@ -2133,6 +2135,7 @@ constexpr int kVcPassRows = 2;
 constexpr int kVcPassTX = 64 - 2 * 2;                                // x halo 2 (two stages)
 constexpr int kVcPassTY = 2 * kVcPassWaves * kVcPassRows - 2 * 2;   // y halo 2
 
+template <bool PROLONG>
 __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_pass(VcPassParams P)
 {
     using T = double;
@@ -2215,7 +2218,13 @@ __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_pass(VcPassParams P
     // their ring slot at the end of the previous step, after stage 2 has
     // finished with the plane that slot held.
     T nph[M][2], nfz[M][2];
-    auto load_early = [&](int t) {
+    // PROLONG: the parent (level l+1) of the pair's rows; planes 2k and 2k+1
+    // share it, so even planes load it (nex) and odd planes reuse it (elast)
+    const int cnx = nx >> 1, cny = ny >> 1;
+    const size_t cplaneP = (size_t)cnx * cny * sizeof(T);
+    const unsigned offE = vrow[0] ? (unsigned)(((ybase >> 1) * cnx + (xl >> 1)) * (int)sizeof(T)) : kOob;
+    T nex = T(0), elast = T(0);
+    auto load_early = [&](int t, bool even) {
         const bool zin = (t >= 0) && (t < nz);
         const bool zinf = (t >= 0) && (t <= nz);   // z faces: nz + 1 planes
         const auto rp = plane_rsrc(P.phi_in, planeP, t, zin);
@@ -2225,6 +2234,8 @@ __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_pass(VcPassParams P
             bload2(rp, offP[r], nph[r][0], nph[r][1]);
             bload2(rz, offP[r], nfz[r][0], nfz[r][1]);
         }
+        if constexpr (PROLONG)
+            if (even) bload1(plane_rsrc(P.ec, cplaneP, t >> 1, zin), offE, nex);
     };
     auto load_late = [&](int t, int slot) {
         const bool zin = (t >= 0) && (t < nz);
@@ -2241,8 +2252,8 @@ __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_pass(VcPassParams P
         for (int r = 0; r <= M; ++r) bload2(ry, offY[r], fy[slot][r][0], fy[slot][r][1]);
     };
 
-    const int tbeg = z0 - S, tend = z1 + S;   // tbeg even (z0 even, S = 2)
-    load_early(tbeg);
+    const int tbeg = z0 - S, tend = z1 + S;   // tbeg even (z0 even, S = 2): plane t has the parity of q
+    load_early(tbeg, true);
     load_late(tbeg, 0);
     for (int tb = tbeg; tb < tend; tb += U) {
 #pragma unroll
@@ -2253,15 +2264,17 @@ __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_pass(VcPassParams P
                 // ---- stage 0: plane t enters the rings; plane t + 1 is requested
                 {
                     const int s0 = q % RP, sf0 = q % RF;
+                    if constexpr (PROLONG)
+                        if ((q & 1) == 0) elast = nex;
 #pragma unroll
                     for (int r = 0; r < M; ++r) {
 #pragma unroll
                         for (int c = 0; c < 2; ++c) {
-                            ph[s0][r][c] = nph[r][c];
+                            ph[s0][r][c] = PROLONG ? nph[r][c] + P.omega * elast : nph[r][c];
                             fz[sf0][r][c] = nfz[r][c];
                         }
                     }
-                    if (t + 1 < tend) load_early(t + 1);
+                    if (t + 1 < tend) load_early(t + 1, (q & 1) == 1);
                     const int ppar = q & 1;   // parity of plane t
                     // black cells of the edge rows: the neighbours the red stage needs
                     edge1[0][par][strip + 1][0][xp] = ph[s0][0][(1 + 0 + ppar) & 1];
