@@ -79,8 +79,8 @@ def run_steps(s, sph_dev, f, phi, w, n):
     stats = None
     for _ in range(n):
         s.deposit(*sph_dev, w.eps, out=f)
-        phi.zero_()
-        _, stats = s.solve(f, phi, rtol=w.rtol, max_cycles=100)
+        # from phi = 0: phi is output only (ccmg_solve_zero)
+        _, stats = s.solve(f, phi, rtol=w.rtol, max_cycles=100, zero_guess=True)
     return stats
 
 

@@ -268,6 +268,17 @@ int ccmg_vcycles(ccmg_solver* s, double* d_phi, const double* d_f, int ncycles, 
 int ccmg_solve(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles,
                ccmg_stats* st);
 
+/* The same solve from the initial guess phi = 0 (Alg. 1 started from zero):
+ * d_phi is output only, its contents on entry are never read.  With the
+ * constant-coefficient FP64 solver the initial residual is b-tilde itself
+ * (its norm pass reads no phi) and the first cycle's finest pre-smoothing
+ * pass starts from zero instead of loading phi; the iterates are those of
+ * ccmg_solve on a zeroed d_phi.  If the solve stops before its first cycle
+ * (||b|| = 0, rtol >= 1, non-finite input) phi is set to 0.  Arguments,
+ * statistics and errors as ccmg_solve. */
+int ccmg_solve_zero(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles,
+                    ccmg_stats* st);
+
 /* Adjoint solve for a loss L(phi): given d_g = dL/dphi, solves A lambda = g
  * with the same operator and homogeneous boundary values (A is symmetric), from
  * lambda = 0, into d_lambda = dL/df.  With n > 0 spheres (same arrays as the

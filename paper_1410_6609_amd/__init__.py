@@ -116,6 +116,7 @@ _SIGS = {
     "ccmg_vcycle": ([_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ccmg_vcycles": ([_VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_solve": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
+    "ccmg_solve_zero": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
     "ccmg_adjoint_solve": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_double, _VP, _VP,
                             ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
     "ccmg_residual": ([_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -350,13 +351,21 @@ class Solver:
         self._face_keep[face] = v   # the copy is stream-ordered: keep the source until it ran
 
     def solve(self, f: torch.Tensor, phi: Optional[torch.Tensor] = None, rtol: float = 1e-10,
-              max_cycles: int = 100, check: bool = True):
-        """Solve A phi = b(f) in place on phi (zeros if None).  Returns (phi, Stats)."""
+              max_cycles: int = 100, check: bool = True, zero_guess: bool = False):
+        """Solve A phi = b(f) in place on phi.  phi holds the initial guess,
+        unless zero_guess is set or phi is None: then the solve starts from
+        phi = 0 (ccmg_solve_zero) and phi is output only.  Returns (phi, Stats)."""
         f = self._field(f, "f")
-        phi = self.zeros() if phi is None else self._field(phi, "phi")
+        if phi is None:
+            nx, ny, nz = self.shape
+            phi = torch.empty((nz, ny, nx), dtype=torch.float64, device=self.device)
+            zero_guess = True
+        else:
+            phi = self._field(phi, "phi")
         st = _Stats()
         self._bind_stream()
-        rc = lib().ccmg_solve(self._h, _ptr(phi), _ptr(f), float(rtol), int(max_cycles), ctypes.byref(st))
+        fn = lib().ccmg_solve_zero if zero_guess else lib().ccmg_solve
+        rc = fn(self._h, _ptr(phi), _ptr(f), float(rtol), int(max_cycles), ctypes.byref(st))
         if check:
             self._check(rc)
         s = Stats(st.cycles, st.inner_cycles, st.rel_res0, st.rel_res, st.seconds, rc)

@@ -262,6 +262,7 @@ bool dispatch<double>(int sphi, int load, int res, const PassParams<double>& P, 
 {
     if (sphi == 0) {
         if (load == LOAD_PHI && res == RES_NORM) { return launch_one<double, 0, LOAD_PHI, RES_NORM>(P, st); }
+        if (load == LOAD_ZERO && res == RES_NORM) { return launch_one<double, 0, LOAD_ZERO, RES_NORM>(P, st); }
         if (load == LOAD_PHI && res == RES_STORE) { return launch_one<double, 0, LOAD_PHI, RES_STORE>(P, st); }
         if (load == LOAD_PHI && res == RES_NORM_R32) { return launch_one<double, 0, LOAD_PHI, RES_NORM_R32>(P, st); }
         if (load == LOAD_CORR && res == RES_NORM_R32) { return launch_one<double, 0, LOAD_CORR, RES_NORM_R32>(P, st); }
@@ -863,21 +864,36 @@ int finish_stats(ccmg_solver* s, const CtlHead& h, int inner_per_step, ccmg_stat
 }
 
 // Whole solve on b-tilde_0 already in the workspace.  phi: initial guess in,
-// solution out.
+// solution out; with zero_guess the guess is phi = 0 and phi is output only.
 int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_stats* st,
-                 std::chrono::steady_clock::time_point t0)
+                 std::chrono::steady_clock::time_point t0, bool zero_guess = false)
 {
-    int rc = enqueue_norm(s, phi, FIN_INIT, RES_NORM, nullptr, nullptr, 0);
-    if (rc) return rc;
     const LevelBuf& B0 = s->lv[0];
-    hipLaunchKernelGGL(k_zero_if_bzero, dim3(grid1d(B0.n)), dim3(256), 0, s->stream, phi, B0.n, (const Ctl*)s->ctl);
+    // constant-coefficient FP64: the residual of the zero guess is b-tilde itself
+    // (the norm pass loads no phi) and the first cycle starts from zero
+    const bool no_load = zero_guess && s->opt.precision == CCMG_FP64 && !s->vc_on;
+    int rc;
+    if (no_load) {
+        PassParams<double> P = base_params<double>(s, 0);
+        P.b = B0.b;
+        P.fin = FIN_INIT;
+        if (!dispatch<double>(0, LOAD_ZERO, RES_NORM, P, s->stream)) return fail(s, CCMG_E_ARG, "norm pass");
+        hipLaunchKernelGGL(k_zero_if_done, dim3(grid1d(B0.n)), dim3(256), 0, s->stream, phi, B0.n,
+                           (const Ctl*)s->ctl);
+    } else {
+        if (zero_guess)
+            hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(B0.n)), dim3(256), 0, s->stream, phi, B0.n, 0.0);
+        if ((rc = enqueue_norm(s, phi, FIN_INIT, RES_NORM, nullptr, nullptr, 0))) return rc;
+        hipLaunchKernelGGL(k_zero_if_bzero, dim3(grid1d(B0.n)), dim3(256), 0, s->stream, phi, B0.n,
+                           (const Ctl*)s->ctl);
+    }
     LAUNCHCHK(s);
     CtlHead h;
     int inner = 1;
     if (s->opt.precision == CCMG_FP64) {
         const LevelPtrs<double> H = fp64_ptrs(s, phi);
         rc = run_loop(s, max_cycles, [&](int k) {
-            return s->vc_on ? enqueue_vc_cycle(s, phi, k) : enqueue_vcycle<double>(s, H, false, k);
+            return s->vc_on ? enqueue_vc_cycle(s, phi, k) : enqueue_vcycle<double>(s, H, no_load && k == 1, k);
         }, h);
     } else {
         inner = s->opt.ir_inner_cycles;
@@ -1495,6 +1511,21 @@ int ccmg_vcycles(ccmg_solver* s, double* d_phi, const double* d_f, int ncycles, 
     if (d_rel_out)
         HIPCHK(s, hipMemcpyAsync(d_rel_out, &s->ctl->rel, sizeof(double), hipMemcpyDeviceToDevice, s->stream));
     return CCMG_OK;
+}
+
+int ccmg_solve_zero(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles, ccmg_stats* st)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    if (max_cycles < 0 || max_cycles > CCMG_MAX_CYCLES) return fail(s, CCMG_E_ARG, "max_cycles out of range");
+    if (!(rtol >= 0.0)) return fail(s, CCMG_E_ARG, "rtol must be >= 0");
+    NEED_DEV(s, d_phi, "d_phi");
+    NEED_DEV(s, d_f, "d_f");
+    if ((rc = enqueue_ctl_init(s, rtol))) return rc;
+    if ((rc = enqueue_fold(s, d_f, false))) return rc;
+    return solve_folded(s, d_phi, rtol, max_cycles, st, t0, true);
 }
 
 int ccmg_solve(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles, ccmg_stats* st)

@@ -1311,6 +1311,16 @@ __global__ void k_fill(T* a, size_t n, T v)
         a[c] = v;
 }
 
+// zero phi when a solve from the zero initial guess stopped before its first
+// cycle (zero right-hand side, rtol >= 1, non-finite input): that guess is
+// never loaded, so nothing else writes phi then
+__global__ void k_zero_if_done(double* a, size_t n, const Ctl* ctl)
+{
+    if (!ctl->done) return;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
+        a[c] = 0.0;
+}
+
 // zero phi when the finest right-hand side vanished (then phi = 0 is the solution)
 __global__ void k_zero_if_bzero(double* a, size_t n, const Ctl* ctl)
 {

@@ -96,6 +96,7 @@ def test_calls_without_workspace_fail_cleanly():
     rc, hd = create((32, 32, 32), ZD)
     assert rc == 0
     assert L.ccmg_solve(hd, None, None, 1e-10, 10, None) == pkg.E_STATE
+    assert L.ccmg_solve_zero(hd, None, None, 1e-10, 10, None) == pkg.E_STATE
     assert L.ccmg_vcycle(hd, None, None, None) == pkg.E_STATE
     assert b"workspace" in L.ccmg_last_error(hd)
     assert L.ccmg_set_face_values(hd, 0, None) == pkg.E_STATE

@@ -1,0 +1,65 @@
+"""Solve from the zero initial guess (ccmg_solve_zero, Alg. 1 started from
+phi = 0): the iterates are those of ccmg_solve on a zeroed phi, bit for bit;
+phi is output only (here filled with NaN beforehand, so a read of it would
+show); and a solve that stops before its first cycle returns phi = 0."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1410_6609_amd as pkg
+from workloads import DIRICHLET as D
+
+from test_gpu_parity import CASES, DEV, ids, log_case, rhs, solver_for, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def nan_field(shape):
+    nx, ny, nz = shape
+    return torch.full((nz, ny, nx), float("nan"), dtype=torch.float64, device=DEV)
+
+
+@pytest.mark.parametrize("precision", [pkg.FP64, pkg.FP32_IR], ids=["fp64", "fp32ir"])
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_solve_zero_matches_zeroed_guess(case, precision):
+    shape, levels, kinds, values = case
+    log_case("solve_zero", shape, precision)
+    s = solver_for(shape, levels, kinds, values, precision=precision)
+    f = to_dev(rhs(shape, 11))
+    p0 = s.zeros()
+    _, st0 = s.solve(f, p0, rtol=1e-10)
+    p1 = nan_field(shape)
+    _, st1 = s.solve(f, p1, rtol=1e-10, zero_guess=True)
+    assert torch.equal(p0, p1)
+    assert (st0.cycles, st0.inner_cycles, st0.rel_res0, st0.rel_res) == \
+        (st1.cycles, st1.inner_cycles, st1.rel_res0, st1.rel_res)
+    # phi = None takes the same path
+    p2, st2 = s.solve(f, rtol=1e-10)
+    assert torch.equal(p0, p2) and st2.cycles == st0.cycles
+
+
+def test_solve_zero_variable_permittivity():
+    shape, levels, kinds, values = CASES[1]
+    log_case("solve_zero vc", shape)
+    s = solver_for(shape, levels, kinds, values, variable_eps=1)
+    eps = np.exp(np.random.default_rng(7).normal(0.0, 1.0, shape[::-1]))
+    s.set_permittivity(to_dev(eps))
+    f = to_dev(rhs(shape, 13))
+    p0 = s.zeros()
+    _, st0 = s.solve(f, p0, rtol=1e-10)
+    p1 = nan_field(shape)
+    _, st1 = s.solve(f, p1, rtol=1e-10, zero_guess=True)
+    assert torch.equal(p0, p1) and st0.cycles == st1.cycles
+
+
+def test_solve_zero_stops_before_first_cycle():
+    shape, levels, kinds, values = CASES[0]
+    log_case("solve_zero early stop", shape)
+    s = solver_for(shape, levels, kinds, values)
+    p = nan_field(shape)
+    _, st = s.solve(to_dev(rhs(shape, 12)), p, rtol=2.0, zero_guess=True)   # rtol >= 1: converged at once
+    assert st.cycles == 0 and bool(torch.all(p == 0))
+    s0 = solver_for(shape, levels, (D,) * 6, (0.0,) * 6)
+    p = nan_field(shape)
+    _, st = s0.solve(s0.zeros(), p, zero_guess=True)                        # zero right-hand side
+    assert st.cycles == 0 and bool(torch.all(p == 0))
