@@ -70,7 +70,7 @@ struct PassParams {
     double* partials;    // RES_NORM*: 2 doubles per block
     int max_partials;    // capacity of `partials` in blocks (checked on the host)
     Ctl* ctl;            // nullable
-    int fin;             // Fin code for the last block
+    int fin;             // Fin code for k_finish_norm (the launch after a norm pass)
     int cycle;           // FIN_CYCLE: cycle index
     int nx, ny, nz;
     int zc;              // planes per block (even)
@@ -437,14 +437,13 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     // byte offsets in a plane: loads (in the domain), stores (owned by this
     // tile), parents of the prolongation and coarse cells of the restriction;
     // kOob where the lane must not access
-    unsigned offL[M], offS[M], offL4[M], offS4[M];
+    unsigned offL[M], offS[M], offL4[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         const unsigned e = (unsigned)((ybase + r) * nx + xl);
         offL[r] = vrow[r] ? e * (unsigned)sizeof(T) : kOob;
         offS[r] = (vrow[r] && yin[r] && xin) ? e * (unsigned)sizeof(T) : kOob;
-        offL4[r] = vrow[r] ? e * 4u : kOob;                    // FP32 correction
-        offS4[r] = (vrow[r] && yin[r] && xin) ? e * 4u : kOob;  // FP32 scaled residual
+        offL4[r] = vrow[r] ? e * 4u : kOob;   // the FP32 correction of LOAD_CORR
     }
     auto coarse_off = [&](int r, bool ok) -> unsigned {
         return ok ? (unsigned)((((ybase + r) >> 1) * cnx + (xl >> 1)) * (int)sizeof(T)) : kOob;
@@ -2097,8 +2096,8 @@ __global__ void k_vc_prolong(double* phi, const double* ec, int nx, int ny, int 
     }
 }
 
-// finest residual norm (and ||b~||) with the last-block finalisation;
-// r_out (nullable) receives the residual times rscale
+// finest residual norm (and ||b~||) as block partials for k_finish_norm (grid-stride form:
+// periodic axes, residual output); r_out (nullable) receives the residual times rscale
 constexpr int kVcNormThreads = 256;
 __global__ __launch_bounds__(kVcNormThreads) void k_vc_norm(VcLevel L, const double* phi, const double* bt,
                                                            double* r_out, double rscale, double* partials, Ctl* ctl,
