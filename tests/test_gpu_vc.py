@@ -18,7 +18,9 @@ from test_gpu_parity import CASES, DEV, ids, log_case, rhs, to_dev
 
 pytestmark = pytest.mark.gpu
 
-VC_CASES = [CASES[1], CASES[3], CASES[4], ((64, 64, 64), 4, (N, N, N, N, D, D), (0, 0, 0, 0, 0.0, 1.0))]
+VC_CASES = [CASES[1], CASES[3], CASES[4], ((64, 64, 64), 4, (N, N, N, N, D, D), (0, 0, 0, 0, 0.0, 1.0)),
+            # every face Dirichlet with its own value; three tiles in x, three in y, many z chunks
+            ((128, 72, 56), 4, (D,) * 6, (0.3, -0.2, 0.5, 1.0, -0.7, 0.1))]
 
 
 def lognormal_eps(shape, seed, sigma=1.2):
