@@ -270,12 +270,14 @@ int ccmg_solve(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, in
 
 /* The same solve from the initial guess phi = 0 (Alg. 1 started from zero):
  * d_phi is output only, its contents on entry are never read.  With the
- * constant-coefficient FP64 solver the initial residual is b-tilde itself
- * (its norm pass reads no phi) and the first cycle's finest pre-smoothing
- * pass starts from zero instead of loading phi; the iterates are those of
- * ccmg_solve on a zeroed d_phi.  If the solve stops before its first cycle
- * (||b|| = 0, rtol >= 1, non-finite input) phi is set to 0.  Arguments,
- * statistics and errors as ccmg_solve. */
+ * closed-form operator (FP64 or FP32-IR) phi is not loaded before it is
+ * first written: the initial residual is b-tilde itself (its norm passes read
+ * no phi), the first FP64 cycle's finest pre-smoothing pass starts from zero
+ * and the first refinement step reads no phi; with variable permittivity phi
+ * is zeroed on the device first.  The iterates are those of ccmg_solve on a
+ * zeroed d_phi.  If no cycle runs (||b|| = 0, rtol >= 1, non-finite input,
+ * max_cycles = 0) phi is set to 0.  Arguments, statistics and errors as
+ * ccmg_solve. */
 int ccmg_solve_zero(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles,
                     ccmg_stats* st);
 

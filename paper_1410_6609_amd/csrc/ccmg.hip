@@ -262,7 +262,6 @@ bool dispatch<double>(int sphi, int load, int res, const PassParams<double>& P, 
 {
     if (sphi == 0) {
         if (load == LOAD_PHI && res == RES_NORM) { return launch_one<double, 0, LOAD_PHI, RES_NORM>(P, st); }
-        if (load == LOAD_ZERO && res == RES_NORM) { return launch_one<double, 0, LOAD_ZERO, RES_NORM>(P, st); }
         if (load == LOAD_PHI && res == RES_STORE) { return launch_one<double, 0, LOAD_PHI, RES_STORE>(P, st); }
         if (load == LOAD_PHI && res == RES_NORM_R32) { return launch_one<double, 0, LOAD_PHI, RES_NORM_R32>(P, st); }
         if (load == LOAD_CORR && res == RES_NORM_R32) { return launch_one<double, 0, LOAD_CORR, RES_NORM_R32>(P, st); }
@@ -869,17 +868,19 @@ int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_
                  std::chrono::steady_clock::time_point t0, bool zero_guess = false)
 {
     const LevelBuf& B0 = s->lv[0];
-    // constant-coefficient FP64: the residual of the zero guess is b-tilde itself
-    // (the norm pass loads no phi) and the first cycle starts from zero
-    const bool no_load = zero_guess && s->opt.precision == CCMG_FP64 && !s->vc_on;
+    // closed-form operator (FP64 or FP32-IR) from the zero guess: phi is never
+    // loaded before it is first written.  The norm passes take a null phi
+    // (read as zero: the residual is b-tilde itself), the first FP64 cycle
+    // starts from zero, and the first refinement step reads a null phi.
+    const bool no_load = zero_guess && !s->vc_on;
     int rc;
     if (no_load) {
-        PassParams<double> P = base_params<double>(s, 0);
-        P.b = B0.b;
-        P.fin = FIN_INIT;
-        if (!dispatch<double>(0, LOAD_ZERO, RES_NORM, P, s->stream)) return fail(s, CCMG_E_ARG, "norm pass");
-        hipLaunchKernelGGL(k_zero_if_done, dim3(grid1d(B0.n)), dim3(256), 0, s->stream, phi, B0.n,
-                           (const Ctl*)s->ctl);
+        if ((rc = enqueue_norm(s, nullptr, FIN_INIT, RES_NORM, nullptr, nullptr, 0))) return rc;
+        if (max_cycles == 0)   // no cycle will write phi: the last iterate is the guess
+            hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(B0.n)), dim3(256), 0, s->stream, phi, B0.n, 0.0);
+        else
+            hipLaunchKernelGGL(k_zero_if_done, dim3(grid1d(B0.n)), dim3(256), 0, s->stream, phi, B0.n,
+                               (const Ctl*)s->ctl);
     } else {
         if (zero_guess)
             hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(B0.n)), dim3(256), 0, s->stream, phi, B0.n, 0.0);
@@ -899,7 +900,7 @@ int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_
         inner = s->opt.ir_inner_cycles;
         const LevelPtrs<float> H = fp32_ptrs(s);
         // first scaled FP32 residual of the initial guess (re-finalises cycle 0)
-        rc = enqueue_norm(s, phi, FIN_CYCLE, RES_NORM_R32, nullptr, s->lv[0].b32, 0);
+        rc = enqueue_norm(s, no_load ? nullptr : phi, FIN_CYCLE, RES_NORM_R32, nullptr, s->lv[0].b32, 0);
         if (rc) return rc;
         double* tmp = s->lv[0].tmp;
         // step k reads the iterate from phi (k odd) or tmp (k even) and writes the other one
@@ -909,7 +910,7 @@ int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_
                 if (r) return r;
             }
             PassParams<double> P = base_params<double>(s, 0);
-            P.phi_in = (k & 1) ? phi : tmp;
+            P.phi_in = (k & 1) ? (no_load && k == 1 ? nullptr : phi) : tmp;
             P.phi_out = (k & 1) ? tmp : phi;
             P.b = s->lv[0].b;
             P.corr = s->lv[0].phi32;

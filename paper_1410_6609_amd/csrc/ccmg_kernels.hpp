@@ -57,7 +57,7 @@ enum Res : int { RES_NONE = 0, RES_RESTRICT = 1, RES_NORM = 2, RES_NORM_R32 = 3,
 // Parameters of the smoother-pass kernel (one struct for every variant).
 template <typename T>
 struct PassParams {
-    const T* phi_in;     // LOAD_PHI / LOAD_PROLONG / LOAD_CORR
+    const T* phi_in;     // LOAD_PHI / LOAD_PROLONG / LOAD_CORR; null reads as zero
     T* phi_out;          // nullable
     const T* b;          // b-tilde of this level
     const T* ec;         // LOAD_PROLONG: coarse correction (level l+1)
@@ -503,7 +503,8 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     auto load_plane = [&](int t, int k, auto oddt) {
         const bool zin = (t >= 0) && (t < nz);
         const auto rb = plane_rsrc(P.b, planeB, t, zin);
-        const auto rp = plane_rsrc(P.phi_in, planeB, t, zin && LOAD != LOAD_ZERO);
+        // a null phi_in reads as zero (the zero initial guess: no load is made)
+        const auto rp = plane_rsrc(P.phi_in, planeB, t, zin && LOAD != LOAD_ZERO && P.phi_in != nullptr);
         const auto rc = plane_rsrc(P.corr, plane * sizeof(float), t, zin && LOAD == LOAD_CORR);
 #pragma unroll
         for (int r = 0; r < M; ++r) {

@@ -52,14 +52,18 @@ def test_solve_zero_variable_permittivity():
     assert torch.equal(p0, p1) and st0.cycles == st1.cycles
 
 
-def test_solve_zero_stops_before_first_cycle():
+@pytest.mark.parametrize("precision", [pkg.FP64, pkg.FP32_IR], ids=["fp64", "fp32ir"])
+def test_solve_zero_stops_before_first_cycle(precision):
     shape, levels, kinds, values = CASES[0]
-    log_case("solve_zero early stop", shape)
-    s = solver_for(shape, levels, kinds, values)
+    log_case("solve_zero early stop", shape, precision)
+    s = solver_for(shape, levels, kinds, values, precision=precision)
     p = nan_field(shape)
     _, st = s.solve(to_dev(rhs(shape, 12)), p, rtol=2.0, zero_guess=True)   # rtol >= 1: converged at once
     assert st.cycles == 0 and bool(torch.all(p == 0))
-    s0 = solver_for(shape, levels, (D,) * 6, (0.0,) * 6)
+    p = nan_field(shape)
+    _, st = s.solve(to_dev(rhs(shape, 12)), p, max_cycles=0, zero_guess=True, check=False)
+    assert st.cycles == 0 and st.status == pkg.E_NOCONV and bool(torch.all(p == 0))   # no cycle allowed
+    s0 = solver_for(shape, levels, (D,) * 6, (0.0,) * 6, precision=precision)
     p = nan_field(shape)
     _, st = s0.solve(s0.zeros(), p, zero_guess=True)                        # zero right-hand side
     assert st.cycles == 0 and bool(torch.all(p == 0))
