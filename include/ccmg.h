@@ -269,12 +269,11 @@ int ccmg_solve(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, in
                ccmg_stats* st);
 
 /* The same solve from the initial guess phi = 0 (Alg. 1 started from zero):
- * d_phi is output only, its contents on entry are never read.  With the
- * closed-form operator (FP64 or FP32-IR) phi is not loaded before it is
- * first written: the initial residual is b-tilde itself (its norm passes read
- * no phi), the first FP64 cycle's finest pre-smoothing pass starts from zero
- * and the first refinement step reads no phi; with variable permittivity phi
- * is zeroed on the device first.  The iterates are those of ccmg_solve on a
+ * d_phi is output only, its contents on entry are never read.  phi is not
+ * loaded before it is first written: the initial residual is b-tilde itself
+ * (its norm passes read no phi), the first cycle's finest pre-smoothing pass
+ * starts from zero and the first refinement step reads no phi; only variable
+ * permittivity on a periodic axis zeroes phi on the device first.  The iterates are those of ccmg_solve on a
  * zeroed d_phi.  If no cycle runs (||b|| = 0, rtol >= 1, non-finite input,
  * max_cycles = 0) phi is set to 0.  Arguments, statistics and errors as
  * ccmg_solve. */

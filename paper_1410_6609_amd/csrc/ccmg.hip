@@ -627,6 +627,7 @@ int enqueue_vc_norm(ccmg_solver* s, const double* phi, int fin, double* r_out, d
             return CCMG_OK;
         }
     }
+    if (phi == nullptr) return fail(s, CCMG_E_ARG, "internal: a zero-guess norm needs the fused residual pass");
     const int g = std::max(1, std::min(vc_grid(s->lv[0].n), s->max_partials));
     hipLaunchKernelGGL(k_vc_norm, dim3(g), dim3(kVcNormThreads), 0, s->stream, vc_level(s, 0), phi,
                        (const double*)s->lv[0].b, r_out, rscale, s->partials, s->ctl, fin, cycle);
@@ -654,7 +655,7 @@ void enqueue_vc_sweeps(ccmg_solver* s, int l, double* phi, int sweeps)
 // applies the prolongation) from one buffer into the other, ending in `home`
 // (a copy when the count is odd); a periodic axis takes the separate
 // prolongation and the colour kernels.
-void enqueue_vc_smooth(ccmg_solver* s, int l, double* home, int sweeps, const double* ec)
+void enqueue_vc_smooth(ccmg_solver* s, int l, double* home, int sweeps, const double* ec, bool zero_in = false)
 {
     const LevelBuf& B = s->lv[l];
     if (s->periodic || sweeps <= 0) {
@@ -689,7 +690,7 @@ void enqueue_vc_smooth(ccmg_solver* s, int l, double* home, int sweeps, const do
     double* buf[2] = {home, B.tmp};
     int cur = 0;
     for (int k = 0; k < sweeps; ++k) {
-        P.phi_in = buf[cur];
+        P.phi_in = (k == 0 && zero_in) ? nullptr : buf[cur];   // zero_in: home holds no guess yet (zero)
         P.phi_out = buf[cur ^ 1];
         if (k == 0 && ec != nullptr)
             hipLaunchKernelGGL(k_vc_pass<true>, dim3(g.blocks()), dim3(64 * kVcPassWaves), 0, s->stream, P);
@@ -702,12 +703,13 @@ void enqueue_vc_smooth(ccmg_solver* s, int l, double* home, int sweeps, const do
                            B.n, (const Ctl*)s->ctl);
 }
 
-int enqueue_vc_cycle(ccmg_solver* s, double* phi0, int fin_cycle)
+// l0_zero: the finest guess is zero and not loaded (no periodic axis)
+int enqueue_vc_cycle(ccmg_solver* s, double* phi0, int fin_cycle, bool l0_zero = false)
 {
     const int L = s->L;
     auto home = [&](int l) { return l == 0 ? phi0 : s->lv[l].phi; };
     for (int l = 0; l + 1 < L; ++l) {
-        enqueue_vc_smooth(s, l, home(l), s->opt.nu1, nullptr);
+        enqueue_vc_smooth(s, l, home(l), s->opt.nu1, nullptr, l == 0 && l0_zero);
         if (!s->periodic) {
             launch_vc_res<true>(s, l, home(l), s->lv[l + 1].b, home(l + 1), 0);
         } else {
@@ -868,11 +870,12 @@ int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_
                  std::chrono::steady_clock::time_point t0, bool zero_guess = false)
 {
     const LevelBuf& B0 = s->lv[0];
-    // closed-form operator (FP64 or FP32-IR) from the zero guess: phi is never
-    // loaded before it is first written.  The norm passes take a null phi
-    // (read as zero: the residual is b-tilde itself), the first FP64 cycle
-    // starts from zero, and the first refinement step reads a null phi.
-    const bool no_load = zero_guess && !s->vc_on;
+    // From the zero guess phi is never loaded before it is first written
+    // (all but variable permittivity on a periodic axis, whose colour kernels
+    // update phi in place): the norm passes take a null phi (read as zero: the
+    // residual is b-tilde itself), the first cycle starts from zero and the
+    // first refinement step reads a null phi.
+    const bool no_load = zero_guess && !(s->vc_on && s->periodic);
     int rc;
     if (no_load) {
         if ((rc = enqueue_norm(s, nullptr, FIN_INIT, RES_NORM, nullptr, nullptr, 0))) return rc;
@@ -894,7 +897,8 @@ int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_
     if (s->opt.precision == CCMG_FP64) {
         const LevelPtrs<double> H = fp64_ptrs(s, phi);
         rc = run_loop(s, max_cycles, [&](int k) {
-            return s->vc_on ? enqueue_vc_cycle(s, phi, k) : enqueue_vcycle<double>(s, H, no_load && k == 1, k);
+            return s->vc_on ? enqueue_vc_cycle(s, phi, k, no_load && k == 1)
+                            : enqueue_vcycle<double>(s, H, no_load && k == 1, k);
         }, h);
     } else {
         inner = s->opt.ir_inner_cycles;

@@ -2243,7 +2243,7 @@ __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_pass(VcPassParams P
     auto load_early = [&](int t, bool even) {
         const bool zin = (t >= 0) && (t < nz);
         const bool zinf = (t >= 0) && (t <= nz);   // z faces: nz + 1 planes
-        const auto rp = plane_rsrc(P.phi_in, planeP, t, zin);
+        const auto rp = plane_rsrc(P.phi_in, planeP, t, zin && P.phi_in != nullptr);   // null: zero guess
         const auto rz = plane_rsrc(L.kz, planeP, t, zinf);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
@@ -2460,7 +2460,7 @@ __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_res(VcResParams P)
     auto load_early = [&](int t) {
         const bool zin = (t >= 0) && (t < nz);
         const bool zinf = (t >= 0) && (t <= nz);
-        const auto rp = plane_rsrc(P.phi, planeP, t, zin);
+        const auto rp = plane_rsrc(P.phi, planeP, t, zin && P.phi != nullptr);   // null: zero guess
         const auto rz = plane_rsrc(L.kz, planeP, t, zinf);
 #pragma unroll
         for (int r = 0; r < M; ++r) {

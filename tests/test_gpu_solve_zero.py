@@ -67,3 +67,20 @@ def test_solve_zero_stops_before_first_cycle(precision):
     p = nan_field(shape)
     _, st = s0.solve(s0.zeros(), p, zero_guess=True)                        # zero right-hand side
     assert st.cycles == 0 and bool(torch.all(p == 0))
+
+
+def test_solve_zero_periodic_variable_permittivity():
+    # periodic x and y: the colour kernels update phi in place, so phi is zeroed first
+    P = pkg.PERIODIC
+    shape, levels = (64, 48, 40), 3
+    kinds, values = (P, P, P, P, D, D), (0.0, 0.0, 0.0, 0.0, 0.2, -0.4)
+    log_case("solve_zero periodic vc", shape)
+    s = solver_for(shape, levels, kinds, values, variable_eps=1)
+    eps = np.exp(np.random.default_rng(8).normal(0.0, 1.0, shape[::-1]))
+    s.set_permittivity(to_dev(eps))
+    f = to_dev(rhs(shape, 14))
+    p0 = s.zeros()
+    _, st0 = s.solve(f, p0, rtol=1e-10)
+    p1 = nan_field(shape)
+    _, st1 = s.solve(f, p1, rtol=1e-10, zero_guess=True)
+    assert torch.equal(p0, p1) and st0.cycles == st1.cycles
