@@ -89,6 +89,8 @@ typedef struct {
                              coarsest run in one workgroup, in LDS (default 4096, the maximum; 0 = off) */
     int variable_eps;     /* 1: reserve stored face coefficients for a cell-wise permittivity
                              (ccmg_set_permittivity; FP64 only); default 0 */
+    double ir_cg_rtol;    /* FP32-IR: coarsest-grid CG tolerance inside the FP32 cycles (default 1e-6:
+                             an FP32 correction carries about seven digits; the FP64 cycles use cg_rtol) */
 } ccmg_options;
 
 typedef struct {

@@ -313,8 +313,10 @@ def solve(b, h, kinds, levels, nu1=2, nu2=2, omega=2.0, rtol=1e-10, max_cycles=1
 
 
 def solve_ir(b, h, kinds, levels, inner=2, nu1=2, nu2=2, omega=2.0, rtol=1e-10, max_outer=100,
-             phi0=None, cg_rtol=1e-13, cg_maxit=None):
-    """FP32-in-FP64 iterative refinement. Returns (phi, history, status)."""
+             phi0=None, cg_rtol=1e-6, cg_maxit=None):
+    """FP32-in-FP64 iterative refinement. Returns (phi, history, status).  cg_rtol is the
+    coarsest CG's tolerance inside the FP32 cycles (the refinement's only CG): 1e-6 by
+    default, as the GPU's, since an FP32 correction carries about seven digits."""
     b = _f64(b)
     phi = np.zeros_like(b) if phi0 is None else _f64(phi0).copy()
     nx, ny, nz = _shape(b)

@@ -51,7 +51,7 @@ class _Options(ctypes.Structure):
                 ("omega", ctypes.c_double), ("precision", ctypes.c_int),
                 ("ir_inner_cycles", ctypes.c_int), ("cg_rtol", ctypes.c_double),
                 ("cg_maxit", ctypes.c_int), ("fuse_sweeps", ctypes.c_int), ("bottom_cells", ctypes.c_int),
-                ("variable_eps", ctypes.c_int)]
+                ("variable_eps", ctypes.c_int), ("ir_cg_rtol", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -73,11 +73,12 @@ class Options:
     fuse_sweeps: int = 2
     bottom_cells: int = 4096
     variable_eps: int = 0
+    ir_cg_rtol: float = 1e-6
 
     def _c(self) -> _Options:
         return _Options(self.nu1, self.nu2, self.levels, self.omega, self.precision,
                         self.ir_inner_cycles, self.cg_rtol, self.cg_maxit, self.fuse_sweeps,
-                        self.bottom_cells, self.variable_eps)
+                        self.bottom_cells, self.variable_eps, self.ir_cg_rtol)
 
 
 @dataclass

@@ -467,7 +467,7 @@ int enqueue_vcycle(ccmg_solver* s, const LevelPtrs<T>& H, bool l0_zero, int fin_
         B.omega = (T)s->opt.omega;
         B.nu1 = s->opt.nu1;
         B.nu2 = s->opt.nu2;
-        B.cg_rtol = s->opt.cg_rtol;
+        B.cg_rtol = sizeof(T) == 4 ? s->opt.ir_cg_rtol : s->opt.cg_rtol;   // the FP32 cycles' own tolerance
         B.cg_maxit = s->cg_maxit;
         B.ctl = s->ctl;
         int nphi = 0, nb = 0;
@@ -481,7 +481,8 @@ int enqueue_vcycle(ccmg_solver* s, const LevelPtrs<T>& H, bool l0_zero, int fin_
         // coarsest level alone
         const int l = L - 1;
         const LevelBuf& B = s->lv[l];
-        launch_cg<T>(H.b[l], H.home[l], B.nx, B.ny, B.nz, s->sh, s->opt.cg_rtol, s->cg_maxit, s->ctl, st);
+        launch_cg<T>(H.b[l], H.home[l], B.nx, B.ny, B.nz, s->sh, sizeof(T) == 4 ? s->opt.ir_cg_rtol : s->opt.cg_rtol,
+                     s->cg_maxit, s->ctl, st);
     }
     // ascend
     for (int l = lbot - 1; l >= 0; --l) {
@@ -1131,6 +1132,7 @@ void ccmg_default_options(ccmg_options* o)
     o->fuse_sweeps = 2;
     o->bottom_cells = kBottomMaxCells;
     o->variable_eps = 0;
+    o->ir_cg_rtol = 1e-6;
 }
 
 int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_face bc[6],
@@ -1148,7 +1150,7 @@ int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_
     if (o.precision != CCMG_FP64 && o.precision != CCMG_FP32_IR) return fail(nullptr, CCMG_E_ARG, "bad precision");
     if (o.ir_inner_cycles < 1 || o.ir_inner_cycles > 16) return fail(nullptr, CCMG_E_ARG, "ir_inner_cycles in 1..16");
     if (o.fuse_sweeps != 1 && o.fuse_sweeps != 2) return fail(nullptr, CCMG_E_ARG, "fuse_sweeps must be 1 or 2");
-    if (!(o.cg_rtol > 0.0) || o.cg_maxit < 0) return fail(nullptr, CCMG_E_ARG, "bad CG options");
+    if (!(o.cg_rtol > 0.0) || !(o.ir_cg_rtol > 0.0) || o.cg_maxit < 0) return fail(nullptr, CCMG_E_ARG, "bad CG options");
     if (!std::isfinite(o.omega)) return fail(nullptr, CCMG_E_ARG, "bad omega");
     if (o.bottom_cells < 0 || o.bottom_cells > kBottomMaxCells)
         return fail(nullptr, CCMG_E_ARG, "bottom_cells must be in 0..%d", kBottomMaxCells);

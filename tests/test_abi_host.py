@@ -160,3 +160,4 @@ def test_defaults():
     assert o.cg_rtol == 1e-13
     assert (o.fuse_sweeps, o.bottom_cells, o.variable_eps) == (2, 4096, 0)
     assert o.ir_inner_cycles == 3
+    assert o.ir_cg_rtol == 1e-6
