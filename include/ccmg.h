@@ -284,7 +284,8 @@ int ccmg_solve_zero(ccmg_solver* s, double* d_phi, const double* d_f, double rto
 
 /* Adjoint solve for a loss L(phi): given d_g = dL/dphi, solves A lambda = g
  * with the same operator and homogeneous boundary values (A is symmetric), from
- * lambda = 0, into d_lambda = dL/df.  With n > 0 spheres (same arrays as the
+ * lambda = 0 (as ccmg_solve_zero: d_lambda is output only, never read), into
+ * d_lambda = dL/df.  With n > 0 spheres (same arrays as the
  * deposition) d_dq (nullable, double[n]) receives dL/dq_s = sum over the
  * sphere's cells of lambda_c / (eps n_s h^3); d_drho (nullable) receives
  * dL/drho = lambda / eps.  Stopping rule, statistics and errors as ccmg_solve. */

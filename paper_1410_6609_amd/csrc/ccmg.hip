@@ -1566,9 +1566,8 @@ int ccmg_adjoint_solve(ccmg_solver* s, const double* d_g, double* d_lambda, int 
     NEED_DEV(s, d_lambda, "d_lambda");
     const size_t n0 = s->lv[0].n;
     if ((rc = enqueue_ctl_init(s, rtol))) return rc;
-    hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(n0)), dim3(256), 0, s->stream, d_lambda, n0, 0.0);
     if ((rc = enqueue_fold(s, d_g, true))) return rc;
-    const int src = solve_folded(s, d_lambda, rtol, max_cycles, st, t0);
+    const int src = solve_folded(s, d_lambda, rtol, max_cycles, st, t0, true);   // from lambda = 0
     if (src != CCMG_OK && src != CCMG_E_NOCONV) return src;
     if (d_drho) {
         NEED_DEV(s, d_drho, "d_drho");
