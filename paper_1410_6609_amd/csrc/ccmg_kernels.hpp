@@ -866,25 +866,6 @@ __device__ __forceinline__ double dpp_d(double v)
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes of a wave, the same value in every lane; fixed
-// association (deterministic): quads, rows of 16 by rotation, then the four
-// row sums in lane order.
-__device__ __forceinline__ double wave_sum_dpp(double v)
-{
-    v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_d<0x124>(v);  // row_ror:4
-    v += dpp_d<0x128>(v);  // row_ror:8
-    double r[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int lo = __builtin_amdgcn_readlane(__double2loint(v), 16 * i);
-        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 16 * i);
-        r[i] = __hiloint2double(hi, lo);
-    }
-    return (r[0] + r[1]) + (r[2] + r[3]);
-}
-
 // Index of cell (i,j,k) in an LDS array with a one-cell zero ghost layer.
 __device__ __forceinline__ int padded(int i, int j, int k, int nx, int ny)
 {
@@ -934,23 +915,39 @@ __device__ __forceinline__ double fast_rcp(double x)
     return fma(y, e, y);
 }
 
-// Two wave sums at once (independent chains interleave).
-__device__ __forceinline__ void wave_sum2_dpp(double& a, double& b)
+// x + (the value of lane l ^ 16) and x + (lane l ^ 32), the lower lane's value
+// first: gfx950's 16- and 32-lane swaps give both operands in every lane.
+__device__ __forceinline__ double add_swap16(double x)
+{
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(x), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(x), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double add_swap32(double x)
+{
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(x), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(x), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double first_lane(double x)
+{
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(x)));
+}
+// Two wave sums over the 64 lanes at once (independent chains interleave),
+// the same value in every lane, in a fixed association (deterministic):
+// quads, rows of 16 by rotation, then the four row sums of lanes 0, 16, 32
+// and 48 combined as (r0 + r1) + (r2 + r3) by the lane swaps, and lane 0's
+// result taken.
+__device__ __forceinline__ void wave_sum2(double& a, double& b)
 {
     a += dpp_d<0xB1>(a); b += dpp_d<0xB1>(b);
     a += dpp_d<0x4E>(a); b += dpp_d<0x4E>(b);
     a += dpp_d<0x124>(a); b += dpp_d<0x124>(b);
     a += dpp_d<0x128>(a); b += dpp_d<0x128>(b);
-    double ra[4], rb[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        ra[i] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(a), 16 * i),
-                                 __builtin_amdgcn_readlane(__double2loint(a), 16 * i));
-        rb[i] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(b), 16 * i),
-                                 __builtin_amdgcn_readlane(__double2loint(b), 16 * i));
-    }
-    a = (ra[0] + ra[1]) + (ra[2] + ra[3]);
-    b = (rb[0] + rb[1]) + (rb[2] + rb[3]);
+    a = add_swap16(a); b = add_swap16(b);
+    a = add_swap32(a); b = add_swap32(b);
+    a = first_lane(a); b = first_lane(b);
 }
 
 // Conjugate gradients in FP64 by ONE wave on a level of n <= 512 cells
@@ -1023,7 +1020,7 @@ __device__ int cg_one_wave(GetB get_b, PutX put_x, double* rl, int nx, int ny, i
             wv[k] = mask * ((double)dg[k] * rv[k] - sum);
             delta += rv[k] * wv[k];
         }
-        wave_sum2_dpp(gamma, delta);
+        wave_sum2(gamma, delta);
         if (it == 0) {
             if (!(gamma > 0.0)) break;                // b = 0: x = 0
             bound = rtol * rtol * gamma;              // ||r||^2 <= rtol^2 ||b||^2
@@ -1182,7 +1179,23 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomParams<T>
     for (int c = threadIdx.x; c < nphi; c += kBottomThreads) ph_all[c] = T(0);
     for (int c = threadIdx.x; c < npl; c += kBottomThreads) pl[c] = 0.0;
     const int n0 = P.nx[0] * P.ny[0] * P.nz[0];
-    for (int c = threadIdx.x; c < n0; c += kBottomThreads) b_all[c] = P.b_in[c];
+    {
+        // every load issued before the first LDS store, so that the thread
+        // waits for one memory latency rather than one per cell (n0 is at
+        // most kBottomMaxCells, checked on the host)
+        constexpr int kLd = kBottomMaxCells / kBottomThreads;
+        T v[kLd];
+#pragma unroll
+        for (int u = 0; u < kLd; ++u) {
+            const int c = threadIdx.x + u * kBottomThreads;
+            v[u] = c < n0 ? P.b_in[c] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kLd; ++u) {
+            const int c = threadIdx.x + u * kBottomThreads;
+            if (c < n0) b_all[c] = v[u];
+        }
+    }
     __syncthreads();
     // descend
     for (int l = 0; l < lc; ++l) {
