@@ -216,6 +216,53 @@ def variable_eps_solve(w: W.Workload, sph, sph_dev, dev, steps: int, warmup: int
             "permittivity": "2.5 inside the 200 spheres, 78.5 elsewhere (jump 31x)"}
 
 
+def forward_adjoint(dev, steps: int, warmup: int, weight_seed: int = 2005):
+    """The microchannel workload (1024 x 256 x 256, 10,000 spheres, 7 levels)
+    as a differentiable step: deposition, the forward solve from zero, then
+    the adjoint solve of the loss L = sum_c w_c phi_c (w ~ N(0,1), seeded)
+    with dL/dq per sphere; FP32 refinement against the plain FP64 solver."""
+    w = W.C5
+    sph = W.workload_spheres(w)
+    c, r, q = (torch.tensor(a, device=dev) for a in (sph.centers, sph.radii, sph.charges))
+    g = torch.tensor(W.random_field(w.shape, weight_seed), device=dev)
+    stream = torch.cuda.current_stream()
+    res, keep = {}, {}
+    for prec, key in ((pkg.FP64, "fp64"), (pkg.FP32_IR, "fp32_ir")):
+        s = make_solver(w, dev, precision=prec)
+        f, phi, lam = s.zeros(), s.zeros(), s.zeros()
+
+        def step():
+            s.deposit(c, r, q, w.eps, out=f)
+            _, st_f = s.solve(f, phi, rtol=w.rtol, max_cycles=100, zero_guess=True)
+            _, dq, _, st_b = s.adjoint(g, c, r, w.eps, rtol=w.rtol, max_cycles=100, lam=lam)
+            return st_f, st_b, dq
+
+        for _ in range(warmup):
+            step()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(steps):
+            st_f, st_b, dq = step()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) / 1e3 / steps
+        _, rel_f = s.residual(phi, f, want_field=False)
+        res[key] = {"ms_per_step": t * 1e3, "solves_per_step": 2, "unknowns_per_s": 2 * w.cells / t,
+                    "forward_cycles": st_f.cycles, "adjoint_cycles": st_b.cycles,
+                    "forward_rel_res_fp64": rel_f, "adjoint_rel_res": st_b.rel_res}
+        keep[key] = (phi.clone(), lam.clone(), dq.clone())
+        del s, f, phi, lam
+        torch.cuda.empty_cache()
+    (p64, l64, d64), (p32, l32, d32) = keep["fp64"], keep["fp32_ir"]
+    res["fp32_ir"]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["fp32_ir"]["ms_per_step"]
+    res["fp32_ir"]["max_abs_diff_phi_vs_fp64"] = (p32 - p64).abs().max().item()
+    res["fp32_ir"]["max_abs_diff_lambda_vs_fp64"] = (l32 - l64).abs().max().item()
+    res["fp32_ir"]["max_rel_diff_dq_vs_fp64"] = ((d32 - d64).abs().max() / d64.abs().max()).item()
+    return {"workload": w.name, "cells": list(w.shape), "spheres": w.n_spheres, "levels": w.levels,
+            "loss": "sum_c w_c phi_c, w ~ N(0,1) per cell (seeded)", **res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,7 +275,9 @@ def main():
     ap.add_argument("--inner", type=int, default=3)
     ap.add_argument("--no-scene", action="store_true", help="skip the time-step scene")
     ap.add_argument("--no-vc", action="store_true", help="skip the variable-permittivity solve")
-    ap.add_argument("--only", choices=("scene", "vc"), default=None,
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the microchannel forward + adjoint step (FP64 and FP32 refinement)")
+    ap.add_argument("--only", choices=("scene", "vc", "adjoint"), default=None,
                     help="run one secondary section alone and print its JSON object (for profiling runs)")
     ap.add_argument("--scene-steps", type=int, default=240)
     ap.add_argument("--calib-copy", action="store_true",
@@ -245,6 +294,9 @@ def main():
     sph_dev = tuple(torch.tensor(a, device=dev) for a in (sph.centers, sph.radii, sph.charges))
     if args.only == "scene":
         print(json.dumps({"timestep_scene": timestep_scene(dev, args.scene_steps)}), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps({"forward_adjoint": forward_adjoint(dev, args.steps, args.warmup)}), flush=True)
         return
     if args.only == "vc":
         print(json.dumps({"variable_eps": variable_eps_solve(w, sph, sph_dev, dev, args.steps, args.warmup)}),
@@ -337,6 +389,11 @@ def main():
     if not args.no_vc:
         out["variable_eps"] = vc = variable_eps_solve(w, sph, sph_dev, dev, max(1, args.steps // 2), 1)
         log(f"variable eps: {vc['ms_per_step']:.3f} ms/step, {vc['cycles']} cycles, rel {vc['final_rel_res']:.2e}")
+
+    if not args.no_adjoint:
+        out["forward_adjoint"] = fa = forward_adjoint(dev, max(1, args.steps // 4), 1)
+        log(f"forward + adjoint ({fa['workload']}): fp64 {fa['fp64']['ms_per_step']:.2f} ms, "
+            f"fp32-ir {fa['fp32_ir']['ms_per_step']:.2f} ms per step")
 
     if not args.no_scene:
         del s
