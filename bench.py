@@ -263,6 +263,71 @@ def forward_adjoint(dev, steps: int, warmup: int, weight_seed: int = 2005):
             "loss": "sum_c w_c phi_c, w ~ N(0,1) per cell (seeded)", **res}
 
 
+def cpu_baseline_all_configs(dev, reps: int = 5):
+    """The CPU-baseline leg for every workload: each solved from zero to 1e-10
+    on the GPU (FP64 and FP32 refinement; deposition included for the sphere
+    workloads) next to the FP64 oracle on the host's cores (all threads; also
+    one thread for the three smaller workloads), with the GPU's largest
+    difference from the oracle."""
+    import oracle
+    oracle.lib()
+    threads = oracle.num_threads()
+    rows = []
+    for w in (W.C1, W.C2, W.C3, W.C4, W.C5):
+        row = {"workload": w.name, "cells": list(w.shape), "levels": w.levels, "spheres": w.n_spheres}
+        if w.n_spheres:
+            sph = W.workload_spheres(w)
+            sph_dev = tuple(torch.tensor(a, device=dev) for a in (sph.centers, sph.radii, sph.charges))
+        else:
+            f_host = W.sine_rhs(w.shape, w.h)
+        phis = {}
+        for prec, key in ((pkg.FP64, "gpu_fp64"), (pkg.FP32_IR, "gpu_fp32_ir")):
+            s = make_solver(w, dev, precision=prec)
+            f = s.zeros() if w.n_spheres else torch.tensor(f_host, device=dev)
+            phi = s.zeros()
+
+            def one():
+                if w.n_spheres:
+                    s.deposit(*sph_dev, w.eps, out=f)
+                return s.solve(f, phi, rtol=w.rtol, max_cycles=100, zero_guess=True)[1]
+
+            for _ in range(2):
+                one()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            torch.cuda.synchronize()
+            ev[0].record(torch.cuda.current_stream())
+            for _ in range(reps):
+                st = one()
+            ev[1].record(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            t = ev[0].elapsed_time(ev[1]) / 1e3 / reps
+            _, rel = s.residual(phi, f, want_field=False)
+            row[key] = {"ms": t * 1e3, "unknowns_per_s": w.cells / t, "cycles": st.cycles,
+                        "rel_res_fp64": rel}
+            phis[key] = phi.cpu().numpy()
+            del s, f, phi
+            torch.cuda.empty_cache()
+        for nthr in ([threads, 1] if w.cells <= 256 ** 3 else [threads]):
+            oracle.set_num_threads(nthr)
+            t0 = time.perf_counter()
+            if w.n_spheres:
+                f_cpu, _ = oracle.deposit(w.shape, w.h, sph.centers, sph.radii, sph.charges, w.eps)
+            else:
+                f_cpu = f_host
+            ref, hist, _ = oracle.solve_problem(f_cpu, w.h, w.kinds, w.values, w.levels, rtol=w.rtol,
+                                                nu1=w.nu1, nu2=w.nu2, omega=w.omega)
+            t = time.perf_counter() - t0
+            row[f"oracle_{nthr}_threads"] = {"s": t, "unknowns_per_s": w.cells / t, "cycles": len(hist) - 1}
+        oracle.set_num_threads(threads)
+        scale = float(np.abs(ref).max())
+        row["max_abs_diff_vs_oracle"] = {k: float(np.abs(v - ref).max()) for k, v in phis.items()}
+        row["max_abs_oracle_phi"] = scale
+        rows.append(row)
+        log(json.dumps(row))
+        del phis, ref
+    return {"cpu_threads": threads, "configs": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +342,8 @@ def main():
     ap.add_argument("--no-vc", action="store_true", help="skip the variable-permittivity solve")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the microchannel forward + adjoint step (FP64 and FP32 refinement)")
+    ap.add_argument("--all-configs", action="store_true",
+                    help="time every workload on the GPU next to the CPU oracle and print that JSON instead")
     ap.add_argument("--only", choices=("scene", "vc", "adjoint"), default=None,
                     help="run one secondary section alone and print its JSON object (for profiling runs)")
     ap.add_argument("--scene-steps", type=int, default=240)
@@ -294,6 +361,9 @@ def main():
     sph_dev = tuple(torch.tensor(a, device=dev) for a in (sph.centers, sph.radii, sph.charges))
     if args.only == "scene":
         print(json.dumps({"timestep_scene": timestep_scene(dev, args.scene_steps)}), flush=True)
+        return
+    if args.all_configs:
+        print(json.dumps(cpu_baseline_all_configs(dev)), flush=True)
         return
     if args.only == "adjoint":
         print(json.dumps({"forward_adjoint": forward_adjoint(dev, args.steps, args.warmup)}), flush=True)
