@@ -98,6 +98,20 @@ def timed(s, sph_dev, f, phi, w, steps):
     return ev0.elapsed_time(ev1) / 1e3, wall, st
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "usable_cores": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(w: W.Workload, sph, budget_s: float = 12.0):
     import oracle
     oracle.lib()
@@ -118,7 +132,7 @@ def cpu_baseline(w: W.Workload, sph, budget_s: float = 12.0):
     return {"value": w.cells / per, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
             "sample": f"{runs} full solve(s) of the same workload (deposit + fold + {cycles} V(2,2)-cycles "
                       f"to 1e-10), {per:.2f} s each, OpenMP threads={cores}",
-            "seconds_per_solve": per}, phi
+            "seconds_per_solve": per, **host_cpu()}, phi
 
 
 def timestep_scene(dev, steps: int):
@@ -325,7 +339,7 @@ def cpu_baseline_all_configs(dev, reps: int = 5):
         rows.append(row)
         log(json.dumps(row))
         del phis, ref
-    return {"cpu_threads": threads, "configs": rows}
+    return {"cpu_threads": threads, **host_cpu(), "configs": rows}
 
 
 def main():
