@@ -433,6 +433,20 @@ def main():
     roofline["other_pass"] = {"kernel": other[1], "avg_launch_us": round(other[2] / max(other[3], 1) * 1e3, 2),
                               "achieved_GBs": round(other[4] * cells / (other[2] / max(other[3], 1) / 1e3) / 1e9, 1)}
 
+    # solve-level fraction: bytes per V(2,2)-cycle over the whole hierarchy
+    # (coarse levels add 1/7) x cycles / (solve time x peak), counted two ways:
+    # the per-sweep floor (every sweep reads phi and b and writes phi, 24 B per
+    # cell, plus 1 B per cell for each grid transfer: 4 x 24 + 2 = 98 B) and the
+    # fused design's own floor (two passes of 25 B)
+    t_solve = t_gpu / args.steps
+    solve_level = {}
+    for key, per_cell in (("per_sweep_floor", 98), ("fused_passes", 50)):
+        b = per_cell * 8 / 7 * cells * st.cycles
+        solve_level[key] = {"bytes_per_cell_per_cycle": round(per_cell * 8 / 7, 1),
+                            "effective_GBs": round(b / t_solve / 1e9, 1),
+                            "frac": round(b / t_solve / 1e9 / HBM_PEAK_GBS, 4)}
+    roofline["solve_level"] = solve_level
+
     out = {
         "metric": "fine-grid unknowns solved/s to 1e-10 rel. residual",
         "value": value,
