@@ -208,3 +208,94 @@ def test_fold_terms(orc):
     phi = np.full((nz, ny, nx), g)
     b = orc.fold(np.zeros((nz, ny, nx)), h, (D,) * 6, (g,) * 6)
     assert np.allclose(orc.apply(phi, h, (D,) * 6), b, rtol=1e-14, atol=0)
+
+
+def multilinear(coef, x, y, z):
+    """phi = c0 + c1 x + c2 y + c3 z + c4 xy + c5 yz + c6 xz + c7 xyz and its
+    three partial derivatives.  phi is linear along every axis, so every second
+    difference of the seven-point stencil vanishes and a boundary ghost value
+    extrapolated linearly through the face (Sec. 2.4) is exact."""
+    c = coef
+    phi = c[0] + c[1] * x + c[2] * y + c[3] * z + c[4] * x * y + c[5] * y * z + c[6] * x * z + c[7] * x * y * z
+    dx = c[1] + c[4] * y + c[6] * z + c[7] * y * z
+    dy = c[2] + c[4] * x + c[5] * z + c[7] * x * z
+    dz = c[3] + c[5] * y + c[6] * x + c[7] * x * y
+    return phi, dx, dy, dz
+
+
+def face_data(coef, shape, h, kinds):
+    """Per-cell boundary values of a multilinear potential at the face centres
+    of the boundary cells: phi there on Dirichlet faces, the outward normal
+    derivative on Neumann faces.  Arrays x faces (nz, ny), y faces (nz, nx),
+    z faces (ny, nx), first index slowest."""
+    nx, ny, nz = shape
+    L = [nx * h, ny * h, nz * h]
+    cx, cy, cz = ((np.arange(n) + 0.5) * h for n in shape)
+    out = []
+    for fc in range(6):
+        ax, hi = fc // 2, fc % 2
+        pos = L[ax] if hi else 0.0
+        if ax == 0:
+            Z, Y = np.meshgrid(cz, cy, indexing="ij")
+            phi, *d = multilinear(coef, np.full_like(Z, pos), Y, Z)
+        elif ax == 1:
+            Z, X = np.meshgrid(cz, cx, indexing="ij")
+            phi, *d = multilinear(coef, X, np.full_like(Z, pos), Z)
+        else:
+            Y, X = np.meshgrid(cy, cx, indexing="ij")
+            phi, *d = multilinear(coef, X, Y, np.full_like(Y, pos))
+        outward = d[ax] if hi else -d[ax]
+        out.append(phi if kinds[fc] == D else outward)
+    return out
+
+
+@pytest.mark.parametrize("kinds", [(D,) * 6, (D, N, N, D, D, N), (N, D, D, N, N, D), (N, N, N, N, D, D),
+                                   (D, D, N, N, N, N)])
+def test_fold_field_reproduces_multilinear_potential(orc, kinds):
+    """Per-cell boundary values (Sec. 2.4 "Boundary conditions"; the validation
+    of Sec. 6.3 sets them per boundary cell): a multilinear potential with its
+    face-centre values on Dirichlet faces and its face-centre outward
+    derivatives on Neumann faces (non-constant on every face) satisfies the
+    folded finite-volume system exactly.  The faces are non-square, so a swap
+    of the two in-face indices, a wrong face or a wrong Neumann sign leaves a
+    residual of the order of the boundary terms."""
+    shape = (6, 10, 8)
+    nx, ny, nz = shape
+    h = 0.3
+    coef = np.random.default_rng(401).uniform(-1.0, 1.0, 8)
+    cx, cy, cz = ((np.arange(n) + 0.5) * h for n in shape)
+    Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+    phi, _, _, _ = multilinear(coef, X, Y, Z)
+    faces = face_data(coef, shape, h, kinds)
+    for a in faces:   # every face array varies over the face
+        assert np.ptp(a) > 0.1
+    b = orc.fold_field(np.zeros((nz, ny, nx)), h, kinds, [0.0] * 6, faces)
+    r = orc.residual(phi, b, h, kinds)
+    assert np.abs(r).max() <= 1e-12 * np.abs(b).max()
+    # the transposed arrays (u and v swapped) must not satisfy it
+    tr = [a.T.copy().reshape(a.shape) for a in faces]
+    r_bad = orc.residual(phi, orc.fold_field(np.zeros((nz, ny, nx)), h, kinds, [0.0] * 6, tr), h, kinds)
+    assert np.abs(r_bad).max() > 1e-3 * np.abs(b).max()
+    # and the multigrid solve of the folded system returns the potential itself
+    sol, hist, st = orc.solve(b, h, kinds, levels=2, rtol=1e-13)
+    assert st == 0
+    assert np.abs(sol - phi).max() <= 1e-11 * np.abs(phi).max()
+
+
+@pytest.mark.parametrize("kinds", [(D,) * 6, (N, D, D, N, D, N)])
+def test_fold_field_constant_arrays_equal_constant_fold(orc, kinds):
+    """Arrays holding each face's constant value give the constant fold bit for
+    bit (same terms, added in the same face order)."""
+    shape = (6, 10, 8)
+    nx, ny, nz = shape
+    h = 0.7
+    values = [0.3, -1.1, 2.5, 0.0, -0.4, 1.7]
+    f = np.random.default_rng(402).standard_normal((nz, ny, nx))
+    shapes = [(nz, ny)] * 2 + [(nz, nx)] * 2 + [(ny, nx)] * 2
+    faces = [np.full(sh, v) for sh, v in zip(shapes, values)]
+    b_const = orc.fold(f, h, kinds, values)
+    b_field = orc.fold_field(f, h, kinds, [99.0] * 6, faces)   # the constants must not be used
+    assert np.array_equal(b_const, b_field)
+    # a face without an array falls back to its constant value
+    mixed = [None, faces[1], None, faces[3], faces[4], None]
+    assert np.array_equal(orc.fold_field(f, h, kinds, values, mixed), b_const)
