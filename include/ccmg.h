@@ -215,6 +215,26 @@ int ccmg_coulomb_adjoint(ccmg_solver* s, const double* d_phi, int n, const doubl
                          const double* d_radii, const double* d_q, int subsample, int mode, const double* d_gF,
                          double* d_mu, double* d_direct);
 
+/* Charge gradient of a loss on the forces, through the whole chain
+ * q -> deposition -> phi = A^-1 b -> F (Sec. 2.4, Eq. ElectrostatForce; the
+ * force is affine in phi and phi is linear in q):
+ *     dL/dq_s = d_direct[s] + sum_c lambda_c w_{s,c} / (eps norm_s),
+ * with d_direct and mu = dL/dphi from ccmg_coulomb_adjoint (force_subsample,
+ * force_mode) and lambda = A^-1 mu from the adjoint solve (homogeneous
+ * boundary values, stopping rule rtol / max_cycles as ccmg_solve), the last
+ * term the deposition's charge gradient (ccmg_charge_gradient with
+ * deposit_subsample, deposit_mode) added on the device.  d_phi: the potential
+ * the forces were computed from; d_gF: dL/dF_s (double[3n]).  Outputs
+ * (device, caller-owned, overwritten): d_mu = dL/dphi and d_lambda = dL/df
+ * (fields [nz][ny][nx]), d_dq = dL/dq (double[n]).  st (nullable): the
+ * adjoint solve's statistics (synchronises).  Returns the adjoint solve's
+ * status: E_NOCONV still fills d_dq from the last iterate of lambda. */
+int ccmg_force_charge_gradient(ccmg_solver* s, const double* d_phi, int n, const double* d_centers,
+                               const double* d_radii, const double* d_q, double eps, int force_subsample,
+                               int force_mode, int deposit_subsample, int deposit_mode, const double* d_gF,
+                               double* d_mu, double* d_lambda, double* d_dq, double rtol, int max_cycles,
+                               ccmg_stats* st);
+
 /* Cell-wise permittivity (extension for discontinuous dielectricity, which
  * the paper's solver is designed for by Galerkin coarsening, Sec. 3, with
  * per-unknown stencils, Sec. 5.3).  Needs a solver created with

@@ -114,6 +114,9 @@ _SIGS = {
     "ccmg_coulomb_adjoint": ([_VP, _VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP],
                              ctypes.c_int),
     "ccmg_coulomb_force": ([_VP, _VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_int, ctypes.c_int, _VP], ctypes.c_int),
+    "ccmg_force_charge_gradient": ([_VP, _VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP, ctypes.c_double,
+                                    ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
     "ccmg_vcycle": ([_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "ccmg_vcycles": ([_VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_solve": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
@@ -321,10 +324,25 @@ class Solver:
     def force_charge_gradient(self, phi: torch.Tensor, centers, radii, q, gF: torch.Tensor, eps: float = 1.0,
                               force_subsample: int = 1, force_mode: int = SPREAD, deposit_subsample: int = 1,
                               deposit_mode: int = SPREAD, rtol: float = 1e-10, max_cycles: int = 100):
-        """dL/dq for a loss on the forces computed from phi = A^-1 b(deposit(q))."""
-        mu, direct = self.coulomb_adjoint(phi, centers, radii, q, gF, force_subsample, force_mode)
-        lam, _, _, _ = self.adjoint(mu, rtol=rtol, max_cycles=max_cycles)
-        return direct + self.charge_gradient(lam, centers, radii, eps, deposit_subsample, deposit_mode)
+        """dL/dq for a loss on the forces computed from phi = A^-1 b(deposit(q))
+        (ccmg_force_charge_gradient: force adjoint, adjoint solve and the
+        deposition's charge gradient, all on the device)."""
+        phi = self._field(phi, "phi")
+        c, r = self._spheres(centers, radii)
+        q = q.to(self.device, torch.float64).contiguous().reshape(-1)
+        gF = gF.to(self.device, torch.float64).contiguous().reshape(-1, 3)
+        n = r.shape[0]
+        if q.shape[0] != n or gF.shape[0] != n:
+            raise ValueError("q, gF and radii disagree in length")
+        mu, lam = self.zeros(), self.zeros()
+        dq = torch.zeros(n, dtype=torch.float64, device=self.device)
+        st = _Stats()
+        self._bind_stream()
+        self._check(lib().ccmg_force_charge_gradient(
+            self._h, _ptr(phi), n, _ptr(c), _ptr(r), _ptr(q), float(eps), int(force_subsample), int(force_mode),
+            int(deposit_subsample), int(deposit_mode), _ptr(gF), _ptr(mu), _ptr(lam), _ptr(dq), float(rtol),
+            int(max_cycles), ctypes.byref(st)))
+        return dq
 
     def set_permittivity(self, eps: Optional[torch.Tensor]) -> None:
         """Cell-wise permittivity (None: back to the constant operator); needs

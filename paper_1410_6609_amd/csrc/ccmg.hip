@@ -837,13 +837,19 @@ int run_loop(ccmg_solver* s, int max_cycles, F enqueue_step, CtlHead& h)
         rc = read_all(s, h);
         if (rc) return rc;
         if (h.done || k >= max_cycles) break;
-        // estimate the remaining cycles from the last contraction
+        if (!(h.rtol > 0.0)) {
+            // no tolerance can stop the loop early (rtol = 0: fixed cycle count)
+            batch = max_cycles - k;
+            continue;
+        }
+        // estimate the remaining cycles from the last contraction, clamped
+        // before the conversion (the logarithm ratio can be huge or infinite)
         const int c = h.cycles;
         const double rate = (c >= 1 && s->hist[c - 1] > 0.0) ? s->hist[c] / s->hist[c - 1] : 0.5;
-        int need = 2;
-        if (rate > 0.0 && rate < 1.0 && h.rel > 0.0)
-            need = (int)std::ceil(std::log(h.rtol / h.rel) / std::log(rate));
-        batch = std::max(1, std::min(need, 64));
+        double need = 2.0;
+        if (rate > 0.0 && rate < 1.0 && h.rel > 0.0) need = std::ceil(std::log(h.rtol / h.rel) / std::log(rate));
+        if (!(need >= 1.0)) need = 1.0;
+        batch = need >= 64.0 ? 64 : (int)need;
     }
     return CCMG_OK;
 }
@@ -1023,11 +1029,11 @@ void launch_deposit_sub(ccmg_solver* s, int n, const double* c, const double* r,
 
 template <int SF>
 void launch_dq_sub(ccmg_solver* s, int n, const double* c, const double* r, double eps, int mode, const double* lam,
-                   double* dq)
+                   double* dq, int accumulate)
 {
     const LevelBuf& B = s->lv[0];
     hipLaunchKernelGGL((k_dq_sub<SF>), dim3(n), dim3(kSphereThreads), 0, s->stream, c, r, eps, s->h, B.nx, B.ny,
-                       B.nz, mode, lam, dq);
+                       B.nz, mode, lam, dq, accumulate);
 }
 
 template <template <int> class K, typename... A>
@@ -1328,7 +1334,7 @@ int ccmg_charge_gradient(ccmg_solver* s, int n, const double* d_centers, const d
     if (n == 0) return CCMG_OK;
     NEED_DEV(s, d_lambda, "d_lambda");
     NEED_DEV(s, d_dq, "d_dq");
-    by_subsample<DqSub>(subsample, s, n, d_centers, d_radii, eps, mode, d_lambda, d_dq);
+    by_subsample<DqSub>(subsample, s, n, d_centers, d_radii, eps, mode, d_lambda, d_dq, 0);
     LAUNCHCHK(s);
     return CCMG_OK;
 }
@@ -1381,6 +1387,38 @@ int ccmg_coulomb_adjoint(ccmg_solver* s, const double* d_phi, int n, const doubl
     }
     LAUNCHCHK(s);
     return CCMG_OK;
+}
+
+int ccmg_force_charge_gradient(ccmg_solver* s, const double* d_phi, int n, const double* d_centers,
+                               const double* d_radii, const double* d_q, double eps, int force_subsample,
+                               int force_mode, int deposit_subsample, int deposit_mode, const double* d_gF,
+                               double* d_mu, double* d_lambda, double* d_dq, double rtol, int max_cycles,
+                               ccmg_stats* st)
+{
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    if ((rc = check_spheres(s, n, d_centers, d_radii, force_subsample, force_mode))) return rc;
+    if ((rc = check_spheres(s, n, d_centers, d_radii, deposit_subsample, deposit_mode))) return rc;
+    if (!(eps > 0.0)) return fail(s, CCMG_E_ARG, "eps must be positive");
+    NEED_DEV(s, d_mu, "d_mu");
+    NEED_DEV(s, d_lambda, "d_lambda");
+    if (n > 0) NEED_DEV(s, d_dq, "d_dq");
+    // mu = dL/dphi through the forces; dq = the direct term at fixed phi
+    if ((rc = ccmg_coulomb_adjoint(s, d_phi, n, d_centers, d_radii, d_q, force_subsample, force_mode, d_gF, d_mu,
+                                   d_dq)))
+        return rc;
+    // lambda = A^-1 mu (homogeneous boundary values), then dq += the
+    // deposition's charge gradient of lambda
+    const int src = ccmg_adjoint_solve(s, d_mu, d_lambda, 0, nullptr, nullptr, eps, nullptr, nullptr, rtol,
+                                       max_cycles, st);
+    if (src != CCMG_OK && src != CCMG_E_NOCONV) return src;
+    if (n > 0) {
+        by_subsample<DqSub>(deposit_subsample, s, n, d_centers, d_radii, eps, deposit_mode, (const double*)d_lambda,
+                            d_dq, 1);
+        LAUNCHCHK(s);
+    }
+    return src;
 }
 
 namespace {
@@ -1473,9 +1511,12 @@ int enqueue_cycle(ccmg_solver* s, double* d_phi, bool norm)
     P.fin = FIN_CYCLE;
     P.cycle = 1;
     if (!dispatch<double>(0, LOAD_CORR, RES_NORM_R32, P, s->stream)) return fail(s, CCMG_E_ARG, "IR pass");
+    // the update landed in tmp unless a non-finite norm stopped the step (then
+    // the update pass did not run, or produced a non-finite residual): the copy
+    // is gated on the same flag, so phi never receives stale or broken data
     const size_t n = s->lv[0].n;
     hipLaunchKernelGGL((k_copy<double>), dim3(grid1d(n)), dim3(256), 0, s->stream, (const double*)s->lv[0].tmp, d_phi,
-                       n, (const Ctl*)nullptr);
+                       n, (const Ctl*)s->ctl);
     LAUNCHCHK(s);
     return CCMG_OK;
 }

@@ -164,7 +164,10 @@ __global__ __launch_bounds__(NT) void k_finish_norm(const double* partials, int 
         ctl->cycles = 0;
         ctl->bzero = finite && (bn == 0.0);
         ctl->status = finite ? 0 : -5;
-        ctl->done = !finite || (bn == 0.0) || !(rel >= ctl->rtol);
+        // a negative rtol marks cycles without a stopping test (single and
+        // warm-started cycles): only a non-finite norm stops them, also when
+        // b vanishes (phi != 0 still has a residual to correct)
+        ctl->done = !finite || (ctl->rtol >= 0.0 && ((bn == 0.0) || !(rel >= ctl->rtol)));
         ctl->sig_next = (finite && rn > 0.0) ? pow2_floor(rn) : 1.0;
     } else if (fin == FIN_CYCLE) {
         ctl->rel = rel;
@@ -1573,11 +1576,12 @@ __global__ __launch_bounds__(kSphereThreads) void k_deposit_sub(const double* ce
     }
 }
 
-// dL/dq_s = sum_c lambda_c w_c / norm_s for the sub-sampled deposition
+// dL/dq_s = sum_c lambda_c w_c / norm_s for the sub-sampled deposition;
+// accumulate != 0 adds it to the value already in dq[s] (dq[s] + term)
 template <int SF>
 __global__ __launch_bounds__(kSphereThreads) void k_dq_sub(const double* centers, const double* radii, double eps,
                                                           double h, int nx, int ny, int nz, int mode,
-                                                          const double* lam, double* dq)
+                                                          const double* lam, double* dq, int accumulate)
 {
 #pragma clang fp contract(off)
     const int s = blockIdx.x;
@@ -1600,7 +1604,10 @@ __global__ __launch_bounds__(kSphereThreads) void k_dq_sub(const double* centers
     }
     const double W = block_sum_d<kSphereThreads>(cnt) / (double)(SF * SF * SF);
     const double sum = block_sum_d<kSphereThreads>(acc);
-    if (threadIdx.x == 0) dq[s] = (mode == 0 && W == 0.0) ? 0.0 : sum / sphere_norm(mode, eps, W, R, h);
+    if (threadIdx.x == 0) {
+        const double g = (mode == 0 && W == 0.0) ? 0.0 : sum / sphere_norm(mode, eps, W, R, h);
+        dq[s] = accumulate ? dq[s] + g : g;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -101,6 +101,8 @@ def test_calls_without_workspace_fail_cleanly():
     assert b"workspace" in L.ccmg_last_error(hd)
     assert L.ccmg_set_face_values(hd, 0, None) == pkg.E_STATE
     assert L.ccmg_vcycles(hd, None, None, 1, None) == pkg.E_STATE
+    assert L.ccmg_force_charge_gradient(hd, None, 0, None, None, None, 1.0, 1, 0, 1, 0, None, None, None, None,
+                                        1e-10, 10, None) == pkg.E_STATE
     L.ccmg_destroy(hd)
 
 

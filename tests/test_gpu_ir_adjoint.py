@@ -235,3 +235,56 @@ def test_vcycles_refinement_steps():
         rel = s.vcycle(b, f)
     assert torch.equal(a, b)
     assert float(rel_dev[0]) == rel
+
+
+@pytest.mark.parametrize("inner", [1, 3])
+def test_fp32_ir_vcycle_matches_oracle_refinement_step(inner):
+    """One FP32-IR cycle call (ccmg_vcycle) is one refinement step: the FP64
+    residual of phi scaled by a power of two, `inner` FP32 V-cycles from zero,
+    the FP64 update.  The oracle's refinement (float arithmetic on the CPU)
+    from the same phi agrees to FP32 rounding of the correction."""
+    shape, levels, kinds, values = CASES[3]
+    log_case("ir vcycle", shape, inner)
+    h = 1.0 / shape[0]
+    s = solver(shape, levels, kinds, values, precision=pkg.FP32_IR, ir_inner_cycles=inner)
+    f = rhs(shape, 64)
+    phi0 = rhs(shape, 65)
+    phi = to_dev(phi0)
+    rel = s.vcycle(phi, to_dev(f))
+    b = oracle.fold(f, h, kinds, values)
+    ref, hist, st = oracle.solve_ir(b, h, kinds, levels, inner=inner, rtol=0.0, max_outer=1, phi0=phi0)
+    assert st == 0 and len(hist) == 2
+    got = phi.cpu().numpy()
+    step = np.abs(ref - phi0).max()
+    assert step > 1e-2 * np.abs(phi0).max()
+    err = np.abs(got - ref).max()
+    print(f"ir vcycle inner={inner}: max|dphi| vs oracle {err:.2e} of a step {step:.2e}", flush=True)
+    assert err <= 1e-5 * step
+    assert abs(rel - hist[1]) <= 1e-3 * hist[1]
+
+
+def test_fp32_ir_vcycle_on_zero_rhs_corrects_phi():
+    """f = 0 with homogeneous boundary values: b vanishes but phi != 0 still has
+    a residual, so the refinement step must update phi (one FP32 cycle gives
+    the FP64 cycle's correction to FP32 accuracy) and never copy stale
+    workspace data into it (an earlier solve leaves its last iterate there)."""
+    shape, levels, kinds, _ = CASES[1]
+    values = (0.0,) * 6
+    log_case("ir vcycle zero rhs", shape)
+    s32 = solver(shape, levels, kinds, values, precision=pkg.FP32_IR, ir_inner_cycles=1)
+    s64 = solver(shape, levels, kinds, values)
+    s32.solve(to_dev(rhs(shape, 67)), rtol=1e-10)       # leaves data in the workspace
+    phi0 = rhs(shape, 68)
+    zero = s64.zeros()
+    a = to_dev(phi0)
+    s64.vcycle(a, zero, norm=False)
+    b_ = to_dev(phi0)
+    rel = s32.vcycle(b_, zero)
+    assert np.isfinite(rel)
+    corr = (a - to_dev(phi0)).abs().max().item()
+    assert corr > 0.1 * np.abs(phi0).max()
+    assert (b_ - a).abs().max().item() <= 1e-4 * corr
+    # vcycles (no host wait) takes the same path
+    c_ = to_dev(phi0)
+    s32.vcycles(c_, zero, 1)
+    assert torch.equal(c_, b_)
