@@ -1,9 +1,10 @@
 """Full-size checks at the benchmark's shapes and launch configuration.
 
-256^3 (FP64): element-wise parity with the oracle after the same cycle count.
-512^3 and 1024x256x256 (FP64 and FP32-IR): the oracle recomputes the FP64
-residual of the GPU solution over the whole grid (a property that holds at any
-size), deposition counts are compared exactly, and the two precisions agree.
+256^3, 512^3 and 1024x256x256: element-wise parity of the FP64 solve with the
+oracle after the same cycle count; the FP32-refined solve against the oracle's
+solution and its own FP64 residual recomputed by the oracle; deposition
+counts compared exactly; the channel's adjoint field and charge gradient
+against the oracle's.
 """
 import numpy as np
 import pytest
@@ -19,8 +20,10 @@ pytestmark = pytest.mark.gpu
 
 
 def make(w, precision=pkg.FP64):
+    """The benchmark's solver configuration for workload w."""
     return pkg.Solver(w.shape, w.h, list(zip(w.kinds, w.values)),
-                      pkg.Options(levels=w.levels, precision=precision), device=DEV)
+                      pkg.Options(levels=w.levels, nu1=w.nu1, nu2=w.nu2, omega=w.omega, precision=precision),
+                      device=DEV)
 
 
 def test_c2_full_parity():
@@ -34,32 +37,80 @@ def test_c2_full_parity():
     f_ref, cnt_ref = oracle.deposit(w.shape, w.h, sph.centers, sph.radii, sph.charges)
     assert np.array_equal(cnt.cpu().numpy(), cnt_ref)
     ref, hist, _ = oracle.solve_problem(f_ref, w.h, w.kinds, w.values, w.levels, rtol=0.0,
-                                        max_cycles=st.cycles)
+                                        max_cycles=st.cycles, nu1=w.nu1, nu2=w.nu2, omega=w.omega)
     assert hist[-1] < 1e-10
     assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("name", ["c3_spheres_512", "c5_channel_1024x256x256"])
-def test_large_workloads_residual_and_precisions(name):
+def test_large_workloads_elementwise_parity(name):
+    """The benchmark's configuration (correction factor, cycle, levels): the
+    GPU's FP64 solve equals the oracle's after the same cycle count to
+    1e-12 of max|phi| at every cell; the FP32-refined solve reaches 1e-10 on
+    the oracle's own FP64 residual and lies within 1e-9 of max|phi| of the
+    oracle's solution (both stop at a relative residual of 1e-10, so their
+    distance is the convergence error, not FP32 rounding)."""
     w = W.ALL[name]
     log_case("full", name)
     sph = W.workload_spheres(w)
     c, r, q = (to_dev(a) for a in (sph.centers, sph.radii, sph.charges))
-    res = {}
+    res, cycles = {}, {}
     for prec in (pkg.FP64, pkg.FP32_IR):
         s = make(w, prec)
         f, cnt = s.deposit(c, r, q, counts=True)
         phi, st = s.solve(f, rtol=w.rtol)
         assert st.rel_res < 1e-10
         res[prec] = phi.cpu().numpy()
-        del s, phi
+        cycles[prec] = st.cycles
+        del s, phi, f
         torch.cuda.empty_cache()
     f_ref, cnt_ref = oracle.deposit(w.shape, w.h, sph.centers, sph.radii, sph.charges)
     assert np.array_equal(cnt.cpu().numpy(), cnt_ref)
+    ref, hist, _ = oracle.solve_problem(f_ref, w.h, w.kinds, w.values, w.levels, rtol=0.0,
+                                        max_cycles=cycles[pkg.FP64], nu1=w.nu1, nu2=w.nu2, omega=w.omega)
+    assert hist[-1] < 1e-10 and hist[-2] >= 1e-10   # the oracle needs the same cycle count
     b = oracle.fold(f_ref, w.h, w.kinds, w.values)
     bn = oracle.norm2(b)
-    for prec, phi in res.items():
-        rel = oracle.norm2(oracle.residual(phi, b, w.h, w.kinds)) / bn
-        assert rel < 1.0001e-10, (prec, rel)
-    scale = np.abs(res[pkg.FP64]).max()
-    assert np.abs(res[pkg.FP32_IR] - res[pkg.FP64]).max() <= 1e-6 * scale
+    scale = np.abs(ref).max()
+    d64 = np.abs(res[pkg.FP64] - ref).max()
+    d32 = np.abs(res[pkg.FP32_IR] - ref).max()
+    rel32 = oracle.norm2(oracle.residual(res[pkg.FP32_IR], b, w.h, w.kinds)) / bn
+    print(f"{name}: FP64 max|dphi| vs oracle {d64:.2e}, FP32-IR {d32:.2e} "
+          f"(max|phi| {scale:.3f}), FP32-IR oracle residual {rel32:.2e}", flush=True)
+    assert d64 <= 1e-12 * scale
+    assert rel32 < 1.0001e-10
+    assert d32 <= 1e-9 * scale
+
+
+def test_channel_adjoint_elementwise_parity():
+    """Adjoint solve on the full 1024x256x256 channel in the benchmark's
+    configuration: lambda equals the oracle's after the same cycle count to
+    1e-12 of max|lambda| and dL/dq to 1e-11 of max|dL/dq|; the FP32-refined
+    adjoint lies within 1e-9 of max|lambda| (both stop at 1e-10)."""
+    w = W.C5
+    log_case("channel adjoint")
+    sph = W.workload_spheres(w)
+    c, r = to_dev(sph.centers), to_dev(sph.radii)
+    g = W.random_field(w.shape, 2005)
+    out = {}
+    for prec in (pkg.FP64, pkg.FP32_IR):
+        s = make(w, prec)
+        lam, dq, _, st = s.adjoint(to_dev(g), c, r, rtol=w.rtol)
+        assert st.rel_res < 1e-10
+        out[prec] = (lam.cpu().numpy(), dq.cpu().numpy(), st.cycles)
+        del s, lam
+        torch.cuda.empty_cache()
+    lam_ref, hist, _ = oracle.adjoint(g, w.h, w.kinds, w.levels, rtol=0.0, max_cycles=out[pkg.FP64][2],
+                                      nu1=w.nu1, nu2=w.nu2, omega=w.omega)
+    dq_ref = oracle.dq(lam_ref, w.h, sph.centers, sph.radii)
+    ls, gs = np.abs(lam_ref).max(), np.abs(dq_ref).max()
+    dl64 = np.abs(out[pkg.FP64][0] - lam_ref).max()
+    dg64 = np.abs(out[pkg.FP64][1] - dq_ref).max()
+    dl32 = np.abs(out[pkg.FP32_IR][0] - lam_ref).max()
+    dg32 = np.abs(out[pkg.FP32_IR][1] - dq_ref).max()
+    print(f"channel adjoint: FP64 max|dlam| {dl64:.2e} max|ddq| {dg64:.2e}; FP32-IR {dl32:.2e} {dg32:.2e} "
+          f"(max|lam| {ls:.3e}, max|dq| {gs:.3e})", flush=True)
+    assert dl64 <= 1e-12 * ls
+    assert dg64 <= 1e-11 * gs
+    assert dl32 <= 1e-9 * ls
+    assert dg32 <= 1e-9 * gs

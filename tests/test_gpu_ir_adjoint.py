@@ -36,7 +36,9 @@ def test_fp32_ir_reaches_fp64_accuracy(case, inner):
     rel = oracle.norm2(oracle.residual(got, b, h, kinds)) / oracle.norm2(b)
     assert rel < 1.0001e-10
     ref, _, _ = oracle.solve(b, h, kinds, levels, rtol=1e-13)
-    assert np.abs(got - ref).max() <= 1e-7 * np.abs(ref).max()
+    # stopping at a relative residual of 1e-10 leaves up to about 1.5e-10 of
+    # max|phi| on these cases (the oracle's own refinement measures the same)
+    assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
     # same refinement algorithm in the oracle (float arithmetic on the CPU)
     _, ohist, ost = oracle.solve_ir(b, h, kinds, levels, inner=inner, rtol=1e-10)
     assert ost == 0 and abs((len(ohist) - 1) - st.cycles) <= 1
