@@ -3,13 +3,17 @@
 One step = the whole hot path on one batch of synthetic input already resident
 in HBM: charge deposition of the spheres, boundary folding of the right-hand
 side and the multigrid solve from phi = 0 to ||b - A phi|| / ||b|| < 1e-10.
-Workload (default): 256^3 cells, Dirichlet phi = 0 / 1 on the z faces and
-zero-Neumann sides, 200 seeded charged spheres of radius 4, plain FP64
-V(2,2)-cycles (correction factor 1.95) down to an 8^3 coarsest grid.
+Workload (default): 512^3 cells, Dirichlet phi = 0 / 1 on the z faces and
+zero-Neumann sides, 2000 seeded charged spheres of radius U[3, 6], plain FP64
+V(2,2)-cycles (correction factor 1.95) down to an 8^3 coarsest grid; the
+largest workload that fits one GPU, with arrays far beyond the caches.
 
 Prints one JSON line.  Also reports the FP32-in-FP64 refinement solve on the
-same input, the live-timed roofline of the dominant kernel and the CPU
-oracle's rate on a bounded sample.
+same input at equal final accuracy, the roofline of the dominant kernel (its
+launches timed with HIP events on the solver's stream in a second pass of
+the same steps, so the headline timing carries no instrumentation), the 256^3
+workload, the variable-permittivity solve, the microchannel forward + adjoint
+step, the time-step scene and the CPU oracle's rate on a bounded sample.
 """
 from __future__ import annotations
 
@@ -112,7 +116,7 @@ def host_cpu() -> dict:
     return {"cpu_model": model, "usable_cores": len(os.sched_getaffinity(0))}
 
 
-def cpu_baseline(w: W.Workload, sph, budget_s: float = 12.0):
+def cpu_baseline(w: W.Workload, sph, budget_s: float = 8.0):
     import oracle
     oracle.lib()
     cores = oracle.num_threads()
@@ -342,17 +346,67 @@ def cpu_baseline_all_configs(dev, reps: int = 5):
     return {"cpu_threads": threads, **host_cpu(), "configs": rows}
 
 
+def small_workload(w: W.Workload, dev, steps: int, warmup: int, inner: int):
+    """Another workload's step (deposition, fold, solve from zero to 1e-10) in
+    FP64 and with FP32 refinement, each timed over the same steps."""
+    sph = W.workload_spheres(w)
+    sph_dev = tuple(torch.tensor(a, device=dev) for a in (sph.centers, sph.radii, sph.charges))
+    res = {"workload": w.name, "cells": list(w.shape), "spheres": w.n_spheres}
+    keep = None
+    for prec, key in ((pkg.FP64, "fp64"), (pkg.FP32_IR, "fp32_ir")):
+        s = make_solver(w, dev, precision=prec, inner=inner)
+        f, phi = s.zeros(), s.zeros()
+        run_steps(s, sph_dev, f, phi, w, warmup)
+        t, _, st = timed(s, sph_dev, f, phi, w, steps)
+        res[key] = {"ms_per_step": t / steps * 1e3, "value": w.cells * steps / t, "unit": "unknowns/s",
+                    "cycles": st.cycles, "final_rel_res": st.rel_res}
+        if keep is None:
+            keep = (s, f, phi)
+        else:
+            _, rel64 = keep[0].residual(phi, f, want_field=False)
+            res[key]["final_rel_res_fp64"] = rel64
+            res[key]["inner_fp32_cycles"] = st.inner_cycles
+            res[key]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res[key]["ms_per_step"]
+            res[key]["max_abs_diff_vs_fp64_solution"] = (phi - keep[2]).abs().max().item()
+    return res
+
+
+def single_thread_oracle():
+    """The oracle on one host thread for the three smaller workloads (sine
+    32^3, 256^3 spheres, 128^3 spheres): deposition, fold and solve to 1e-10."""
+    import oracle
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    rows = {}
+    try:
+        for w in (W.C1, W.C2, W.C4):
+            t0 = time.perf_counter()
+            if w.n_spheres:
+                sph = W.workload_spheres(w)
+                f, _ = oracle.deposit(w.shape, w.h, sph.centers, sph.radii, sph.charges, w.eps)
+            else:
+                f = W.sine_rhs(w.shape, w.h)
+            _, hist, _ = oracle.solve_problem(f, w.h, w.kinds, w.values, w.levels, rtol=w.rtol, nu1=w.nu1,
+                                              nu2=w.nu2, omega=w.omega)
+            t = time.perf_counter() - t0
+            rows[w.name] = {"s": t, "unknowns_per_s": w.cells / t, "cycles": len(hist) - 1}
+    finally:
+        oracle.set_num_threads(threads)
+    return {"threads": 1, "workloads": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=W.C2.name, choices=sorted(W.ALL))
+    ap.add_argument("--workload", default=W.C3.name, choices=sorted(W.ALL))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ir", action="store_true", help="skip the FP32-IR comparison")
     ap.add_argument("--fuse", type=int, default=2)
     ap.add_argument("--inner", type=int, default=3)
     ap.add_argument("--no-scene", action="store_true", help="skip the time-step scene")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 256^3 workload section")
     ap.add_argument("--no-vc", action="store_true", help="skip the variable-permittivity solve")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the microchannel forward + adjoint step (FP64 and FP32 refinement)")
@@ -399,18 +453,27 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    s.profile(True)
-    s.profile_read(0)
-    s.profile_read(1)
+    # headline: the timed steps carry no instrumentation
     t_gpu, wall, st = timed(s, sph_dev, f, phi, w, args.steps)
-    ms0, n0 = s.profile_read(0)
-    ms1, n1 = s.profile_read(1)
-    s.profile(False)
     ms_step = t_gpu / args.steps * 1e3
     value = w.cells * args.steps / t_gpu
     log(f"fp64: {ms_step:.3f} ms/step, {st.cycles} cycles, rel {st.rel_res:.2e}, wall {wall:.3f}s")
+    # the same steps again with every finest-level pass bracketed by HIP events
+    # on the solver's stream: per-launch durations of the dominant kernel
+    s.profile(True)
+    s.profile_read(0)
+    s.profile_read(1)
+    t_prof, _, _ = timed(s, sph_dev, f, phi, w, args.steps)
+    ms0, n0 = s.profile_read(0)
+    ms1, n1 = s.profile_read(1)
+    s.profile(False)
 
-    # roofline of the dominant kernel: the finest-level fused pass with the larger total time
+    # roofline of the dominant kernel: the finest-level fused pass with the
+    # larger total time.  Algorithmic bytes per launch in two units: the
+    # per-sweep unit (every red-black sweep reads phi and b and writes phi,
+    # 24 B per cell, plus 1 B per cell for the fused grid transfer: 49 B for
+    # the two sweeps of one launch) and the fused pass's own floor (phi and b
+    # read once, phi written once, plus the transfer: 25 B)
     cells = w.cells
     passes = [
         ("pre", "pre-smoothing pass (2 RB-GS sweeps + residual + restriction), finest level", ms0, n0,
@@ -420,24 +483,40 @@ def main():
     ]
     which, name, ms_k, n_k, bpc = max(passes, key=lambda p: p[2])
     avg_s = ms_k / max(n_k, 1) / 1e3
-    bytes_per_launch = bpc * cells
-    achieved = bytes_per_launch / avg_s / 1e9
+    unit_bpc = 2 * 24 + 1
+    achieved = unit_bpc * cells / avg_s / 1e9
+    fused = bpc * cells / avg_s / 1e9
     hbm = measured_traffic(w.name, which)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if hbm is None else round(hbm / avg_s / 1e9, 1),
                 "kernel": name, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_k,
-                "algorithmic_bytes_per_cell": bpc, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "hbm_bytes_per_launch": hbm}
+                "units": {"frac": f"per-sweep unit: 2 sweeps x 24 B + 1 B transfer = {unit_bpc} B per cell "
+                                  "per launch (exceeds 1 when the fused pass beats separate sweeps)",
+                          "frac_fused_floor": f"the fused pass's own floor: {bpc} B per cell per launch "
+                                              "(phi and b read once, phi written once, 1 B transfer)",
+                          "traffic": "counted HBM bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE) "
+                                     "/ average launch time"},
+                "frac_fused_floor": round(fused / HBM_PEAK_GBS, 4), "achieved_fused_floor": round(fused, 1),
+                "algorithmic_bytes_per_launch": unit_bpc * cells,
+                "fused_floor_bytes_per_launch": bpc * cells,
+                "hbm_bytes_per_launch": hbm,
+                "hbm_bytes_over_fused_floor": None if hbm is None else round(hbm / (bpc * cells), 3)}
     other = [p for p in passes if p[0] != which][0]
-    roofline["other_pass"] = {"kernel": other[1], "avg_launch_us": round(other[2] / max(other[3], 1) * 1e3, 2),
-                              "achieved_GBs": round(other[4] * cells / (other[2] / max(other[3], 1) / 1e3) / 1e9, 1)}
+    o_s = other[2] / max(other[3], 1) / 1e3
+    hbm_o = measured_traffic(w.name, other[0])
+    roofline["other_pass"] = {"kernel": other[1], "avg_launch_us": round(o_s * 1e6, 2),
+                              "frac": round(unit_bpc * cells / o_s / 1e9 / HBM_PEAK_GBS, 4),
+                              "frac_fused_floor": round(other[4] * cells / o_s / 1e9 / HBM_PEAK_GBS, 4),
+                              "traffic": None if hbm_o is None else round(hbm_o / o_s / 1e9, 1),
+                              "hbm_bytes_over_fused_floor": None if hbm_o is None
+                              else round(hbm_o / (other[4] * cells), 3)}
+    roofline["finest_passes_share_of_step"] = round((ms0 + ms1) / (t_prof * 1e3), 4)
 
     # solve-level fraction: bytes per V(2,2)-cycle over the whole hierarchy
     # (coarse levels add 1/7) x cycles / (solve time x peak), counted two ways:
-    # the per-sweep floor (every sweep reads phi and b and writes phi, 24 B per
-    # cell, plus 1 B per cell for each grid transfer: 4 x 24 + 2 = 98 B) and the
-    # fused design's own floor (two passes of 25 B)
+    # the per-sweep floor (4 x 24 + 2 = 98 B) and the fused design's own floor
+    # (two passes of 25 B)
     t_solve = t_gpu / args.steps
     solve_level = {}
     for key, per_cell in (("per_sweep_floor", 98), ("fused_passes", 50)):
@@ -484,8 +563,17 @@ def main():
             f"max|dphi| vs fp64 {diff:.2e}")
         del s32, phi32
 
+    if w.name != W.C2.name and not args.no_c2:
+        del s
+        torch.cuda.empty_cache()
+        out["c2_spheres_256"] = c2 = small_workload(W.C2, dev, args.steps, args.warmup, args.inner)
+        log(f"256^3: fp64 {c2['fp64']['ms_per_step']:.3f} ms, fp32-ir {c2['fp32_ir']['ms_per_step']:.3f} ms per step")
+
     if not args.no_vc:
-        out["variable_eps"] = vc = variable_eps_solve(w, sph, sph_dev, dev, max(1, args.steps // 2), 1)
+        wv = W.C2
+        sph_v = W.workload_spheres(wv)
+        sph_vd = tuple(torch.tensor(a, device=dev) for a in (sph_v.centers, sph_v.radii, sph_v.charges))
+        out["variable_eps"] = vc = variable_eps_solve(wv, sph_v, sph_vd, dev, max(1, args.steps // 2), 1)
         log(f"variable eps: {vc['ms_per_step']:.3f} ms/step, {vc['cycles']} cycles, rel {vc['final_rel_res']:.2e}")
 
     if not args.no_adjoint:
@@ -494,7 +582,7 @@ def main():
             f"fp32-ir {fa['fp32_ir']['ms_per_step']:.2f} ms per step")
 
     if not args.no_scene:
-        del s
+        s = None
         torch.cuda.empty_cache()
         out["timestep_scene"] = ts = timestep_scene(dev, args.scene_steps)
         log(f"time-step scene: {ts['ms_per_step']:.3f} ms/step, {ts['mlups']:.0f} MLUPS, "
@@ -503,6 +591,7 @@ def main():
     if not args.no_cpu:
         base, phi_cpu = cpu_baseline(w, sph)
         base["max_abs_diff_gpu_vs_oracle"] = float(np.abs(phi.cpu().numpy() - phi_cpu).max())
+        base["single_thread"] = single_thread_oracle()
         out["cpu_baseline"] = base
         log(f"cpu oracle: {base['seconds_per_solve']:.2f} s/solve on {base['cores']} threads")
 
