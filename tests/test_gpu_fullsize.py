@@ -86,7 +86,8 @@ def test_channel_adjoint_elementwise_parity():
     """Adjoint solve on the full 1024x256x256 channel in the benchmark's
     configuration: lambda equals the oracle's after the same cycle count to
     1e-12 of max|lambda| and dL/dq to 1e-11 of max|dL/dq|; the FP32-refined
-    adjoint lies within 1e-9 of max|lambda| (both stop at 1e-10)."""
+    adjoint, which overshoots the tolerance, lies within 1e-9 of the oracle's
+    converged lambda and dL/dq."""
     w = W.C5
     log_case("channel adjoint")
     sph = W.workload_spheres(w)
@@ -100,14 +101,20 @@ def test_channel_adjoint_elementwise_parity():
         out[prec] = (lam.cpu().numpy(), dq.cpu().numpy(), st.cycles)
         del s, lam
         torch.cuda.empty_cache()
-    lam_ref, hist, _ = oracle.adjoint(g, w.h, w.kinds, w.levels, rtol=0.0, max_cycles=out[pkg.FP64][2],
-                                      nu1=w.nu1, nu2=w.nu2, omega=w.omega)
+    kw = dict(nu1=w.nu1, nu2=w.nu2, omega=w.omega)
+    lam_ref, hist, _ = oracle.adjoint(g, w.h, w.kinds, w.levels, rtol=0.0, max_cycles=out[pkg.FP64][2], **kw)
     dq_ref = oracle.dq(lam_ref, w.h, sph.centers, sph.radii)
+    # the FP64 solve stops just below 1e-10, the refinement lands far lower
+    # (its last step holds three cycles): compare it with the oracle's
+    # solution carried four cycles further
+    lam_conv, hist2, _ = oracle.adjoint(g, w.h, w.kinds, w.levels, rtol=0.0, max_cycles=4, phi0=lam_ref, **kw)
+    assert hist2[-1] < 1e-13
+    dq_conv = oracle.dq(lam_conv, w.h, sph.centers, sph.radii)
     ls, gs = np.abs(lam_ref).max(), np.abs(dq_ref).max()
     dl64 = np.abs(out[pkg.FP64][0] - lam_ref).max()
     dg64 = np.abs(out[pkg.FP64][1] - dq_ref).max()
-    dl32 = np.abs(out[pkg.FP32_IR][0] - lam_ref).max()
-    dg32 = np.abs(out[pkg.FP32_IR][1] - dq_ref).max()
+    dl32 = np.abs(out[pkg.FP32_IR][0] - lam_conv).max()
+    dg32 = np.abs(out[pkg.FP32_IR][1] - dq_conv).max()
     print(f"channel adjoint: FP64 max|dlam| {dl64:.2e} max|ddq| {dg64:.2e}; FP32-IR {dl32:.2e} {dg32:.2e} "
           f"(max|lam| {ls:.3e}, max|dq| {gs:.3e})", flush=True)
     assert dl64 <= 1e-12 * ls
