@@ -255,7 +255,7 @@ def test_fp32_ir_vcycle_matches_oracle_refinement_step(inner):
     rel = s.vcycle(phi, to_dev(f))
     b = oracle.fold(f, h, kinds, values)
     ref, hist, st = oracle.solve_ir(b, h, kinds, levels, inner=inner, rtol=0.0, max_outer=1, phi0=phi0)
-    assert st == 0 and len(hist) == 2
+    assert st in (oracle.OK, oracle.E_NOCONV) and len(hist) == 2   # rtol = 0: one step, never "converged"
     got = phi.cpu().numpy()
     step = np.abs(ref - phi0).max()
     assert step > 1e-2 * np.abs(phi0).max()
