@@ -302,6 +302,28 @@ int ccmg_solve(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, in
 int ccmg_solve_zero(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles,
                     ccmg_stats* st);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc), and so
+ * cannot provide the workspace of ccmg_set_workspace: the solve of
+ * ccmg_solve_zero with the solver's workspace carved for the duration of the
+ * call from a static device array of CCMG_STATIC_SCRATCH_BYTES bytes that the
+ * library holds on every device it runs on until the process ends.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine);
+ * the caller still passes d_phi (output only) and d_f.  No workspace needs to
+ * be attached; an attached one is left untouched and in use for every other
+ * call.  Same kernels, iterates, statistics and errors as ccmg_solve_zero.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents; the call synchronises the solver's stream before it
+ * returns, and calls that overlap on one device (from several threads or
+ * streams) race.  Errors: E_ARG if ccmg_workspace_bytes(s) exceeds
+ * CCMG_STATIC_SCRATCH_BYTES (checked before any device work: attach a
+ * workspace and call ccmg_solve_zero instead); E_STATE for solvers whose
+ * solve needs data kept in an attached workspace (per-cell boundary values,
+ * variable permittivity, periodic faces); otherwise as ccmg_solve_zero. */
+#define CCMG_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int ccmg_solve_zero_static(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles,
+                           ccmg_stats* st);
+
 /* Adjoint solve for a loss L(phi): given d_g = dL/dphi, solves A lambda = g
  * with the same operator and homogeneous boundary values (A is symmetric), from
  * lambda = 0 (as ccmg_solve_zero: d_lambda is output only, never read), into

@@ -121,6 +121,7 @@ _SIGS = {
     "ccmg_vcycles": ([_VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "ccmg_solve": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
     "ccmg_solve_zero": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
+    "ccmg_solve_zero_static": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
     "ccmg_adjoint_solve": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_double, _VP, _VP,
                             ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
     "ccmg_residual": ([_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -169,7 +170,7 @@ class Solver:
     """
 
     def __init__(self, shape: Tuple[int, int, int], h: float, faces: Sequence[Tuple[int, float]],
-                 options: Optional[Options] = None, device="cuda"):
+                 options: Optional[Options] = None, device="cuda", workspace: bool = True):
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("the solver runs on a GPU device only")
@@ -191,6 +192,9 @@ class Solver:
             raise CcmgError(rc, L.ccmg_last_error(None).decode())
         self._h = handle
         nbytes = L.ccmg_workspace_bytes(handle)
+        self.workspace = None
+        if not workspace:   # only solve_static() can run: it uses the library's static scratch
+            return
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         aligned = (base + 255) & ~255
@@ -389,6 +393,21 @@ class Solver:
             self._check(rc)
         s = Stats(st.cycles, st.inner_cycles, st.rel_res0, st.rel_res, st.seconds, rc)
         return phi, s
+
+    def solve_static(self, f: torch.Tensor, phi: torch.Tensor, rtol: float = 1e-10, max_cycles: int = 100,
+                     check: bool = True):
+        """The solve from phi = 0 on the library's static device scratch
+        (ccmg_solve_zero_static): no device memory is allocated, here or in the
+        library; phi (output) and f are the caller's.  Returns (phi, Stats)."""
+        f = self._field(f, "f")
+        phi = self._field(phi, "phi")
+        st = _Stats()
+        self._bind_stream()
+        rc = lib().ccmg_solve_zero_static(self._h, _ptr(phi), _ptr(f), float(rtol), int(max_cycles),
+                                          ctypes.byref(st))
+        if check:
+            self._check(rc)
+        return phi, Stats(st.cycles, st.inner_cycles, st.rel_res0, st.rel_res, st.seconds, rc)
 
     def vcycle(self, phi: torch.Tensor, f: torch.Tensor, norm: bool = True) -> Optional[float]:
         f = self._field(f, "f")

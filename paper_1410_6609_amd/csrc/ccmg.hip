@@ -20,6 +20,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1013,6 +1014,45 @@ int check_ready(ccmg_solver* s)
 
 }  // namespace
 
+// Workspace of the allocation-free solve (ccmg_solve_zero_static): one copy
+// per device, resident while the process lives.  In host code this name is
+// only a handle for hipGetSymbolAddress, never a device address.
+static __device__ __align__(256) char scratch[CCMG_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// Device address of the current device's scratch array, resolved once per
+// device with that device current; also refreshes the CU count the pass
+// grids are sized for.
+int static_scratch(ccmg_solver* s, char** out)
+{
+    int dev = 0;
+    HIPCHK(s, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(s, CCMG_E_ARG, "device ordinal %d beyond %d", dev, kMaxDevices);
+    {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        if (g_scratch_ptr[dev] == nullptr) {
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || p == nullptr)
+                return fail(s, CCMG_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            if (((uintptr_t)p & 255) != 0) return fail(s, CCMG_E_HIP, "internal: scratch not 256-byte aligned");
+            g_scratch_ptr[dev] = static_cast<char*>(p);
+        }
+        *out = g_scratch_ptr[dev];
+    }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) g_num_cus = ncu;
+    (void)hipGetLastError();
+    return CCMG_OK;
+}
+
+}  // namespace
+
 // ============================================================================
 // C ABI
 // ============================================================================
@@ -1574,6 +1614,45 @@ int ccmg_solve_zero(ccmg_solver* s, double* d_phi, const double* d_f, double rto
     if ((rc = enqueue_ctl_init(s, rtol))) return rc;
     if ((rc = enqueue_fold(s, d_f, false))) return rc;
     return solve_folded(s, d_phi, rtol, max_cycles, st, t0, true);
+}
+
+int ccmg_solve_zero_static(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles,
+                           ccmg_stats* st)
+{
+    if (!s) return CCMG_E_ARG;
+    s->err.clear();
+    // host-side checks first: nothing runs on the device for a rejected call
+    if (s->need_bytes > CCMG_STATIC_SCRATCH_BYTES)
+        return fail(s, CCMG_E_ARG,
+                    "workspace of %zu bytes exceeds the static scratch of %zu bytes: attach a workspace and call "
+                    "ccmg_solve_zero", s->need_bytes, (size_t)CCMG_STATIC_SCRATCH_BYTES);
+    if (s->periodic || s->vc_on)
+        return fail(s, CCMG_E_STATE, "periodic faces and variable permittivity keep their face coefficients in "
+                                     "the attached workspace: use ccmg_solve_zero");
+    for (int fc = 0; fc < 6; ++fc)
+        if (s->face_on[fc])
+            return fail(s, CCMG_E_STATE, "per-cell boundary values (face %d) live in the attached workspace: use "
+                                         "ccmg_solve_zero", fc);
+    char* p = nullptr;
+    int rc = static_scratch(s, &p);
+    if (rc) return rc;
+    // carve the workspace from the scratch for this call, then restore the
+    // caller's layout (or none: other entry points keep failing with E_STATE)
+    char* const old_ws = s->ws;
+    const size_t old_bytes = s->ws_bytes;
+    layout_workspace(s, p);
+    s->ws = p;
+    s->ws_bytes = CCMG_STATIC_SCRATCH_BYTES;
+    rc = ccmg_solve_zero(s, d_phi, d_f, rtol, max_cycles, st);
+    if (rc != CCMG_OK && rc != CCMG_E_NOCONV && rc != CCMG_E_NONFINITE) {
+        // an early error return may leave work queued that uses the scratch
+        (void)hipStreamSynchronize(s->stream);
+        (void)hipGetLastError();
+    }
+    if (old_ws != nullptr) layout_workspace(s, old_ws);
+    s->ws = old_ws;
+    s->ws_bytes = old_bytes;
+    return rc;
 }
 
 int ccmg_solve(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles, ccmg_stats* st)

@@ -163,3 +163,21 @@ def test_defaults():
     assert (o.fuse_sweeps, o.bottom_cells, o.variable_eps) == (2, 4096, 0)
     assert o.ir_inner_cycles == 3
     assert o.ir_cg_rtol == 1e-6
+
+
+def test_static_scratch_solve_rejects_before_device_work():
+    """The allocation-free solve checks the workspace size against its static
+    scratch, and the solver kinds whose data live in an attached workspace,
+    on the host: no device is touched for a rejected call."""
+    L = pkg.lib()
+    rc, hd = create((512, 512, 512), ZD)
+    assert rc == 0 and L.ccmg_workspace_bytes(hd) > (64 << 20)
+    rc = L.ccmg_solve_zero_static(hd, None, None, 1e-10, 10, None)
+    assert rc == pkg.E_ARG
+    assert b"static scratch" in L.ccmg_last_error(hd)
+    L.ccmg_destroy(hd)
+    rc, hd = create((32, 32, 32), (2, 2, 1, 1, 0, 0))   # periodic x
+    assert rc == 0 and L.ccmg_workspace_bytes(hd) <= (64 << 20)
+    assert L.ccmg_solve_zero_static(hd, None, None, 1e-10, 10, None) == pkg.E_STATE
+    assert b"periodic" in L.ccmg_last_error(hd)
+    L.ccmg_destroy(hd)
