@@ -69,10 +69,11 @@ struct Grid {
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // Tile-and-chunk decomposition of one pass with S stages over an nx*ny*nz
-// level.  A block owning zc planes marches zc + 2S steps (the z halo costs 2S),
-// and blocks run in rounds of `capacity` (CUs x resident blocks per CU).  The
-// chunking minimises rounds x (zc + 2S): long chunks on large levels, short
-// ones (more blocks, fewer sequential steps) on small, latency-bound levels.
+// level.  A block owning zc planes marches zc + 2S steps (the z halo costs
+// 2S), and blocks run in rounds of `capacity` (CUs x resident blocks per CU).
+// The chunking minimises rounds x (zc + 2S): long chunks on large levels,
+// short ones (more blocks, fewer sequential steps) on small, latency-bound
+// levels.
 Grid pass_grid(int nx, int ny, int nz, int tx, int ty, int S, int capacity)
 {
     Grid g;
@@ -194,6 +195,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // ---------------------------------------------------------------------------
 int g_num_cus = 256;   // set from the device at workspace attachment
 constexpr size_t kBottomMaxLds = 160 * 1024;
+constexpr int kPadMinPlanes = 64;   // z-chunks from which FP64 passes march whole unrolled blocks
 
 template <typename T, int SPHI, int LOAD, int RES>
 bool launch_one(const PassParams<T>& P0, hipStream_t st)
@@ -221,7 +223,12 @@ bool launch_one(const PassParams<T>& P0, hipStream_t st)
     // the norm reduction stores one partial per block, then one workgroup adds them
     constexpr bool kNormRes = RES == RES_NORM || RES == RES_NORM_R32 || RES == RES_STORE;
     if (kNormRes && g.blocks() > P.max_partials) return false;
-    hipLaunchKernelGGL(kern, dim3(g.blocks()), dim3(64 * WYT), 0, st, P);
+    // long FP64 marches run whole unrolled blocks of steps (k_pass PAD)
+    constexpr bool kPadKernel = sizeof(T) == 8 && SPHI > 0;
+    if (kPadKernel && g.zc >= kPadMinPlanes)
+        hipLaunchKernelGGL((k_pass<T, SPHI, LOAD, RES, kM, WYT, kPadKernel>), dim3(g.blocks()), dim3(64 * WYT), 0, st, P);
+    else
+        hipLaunchKernelGGL(kern, dim3(g.blocks()), dim3(64 * WYT), 0, st, P);
     if constexpr (kNormRes)
         hipLaunchKernelGGL(k_finish_norm<64 * WYT>, dim3(1), dim3(64 * WYT), 0, st, (const double*)P.partials,
                            g.blocks(), P.ctl, P.fin, P.cycle, 1);

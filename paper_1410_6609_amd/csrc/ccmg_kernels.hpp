@@ -363,7 +363,12 @@ struct PassShape {
 #define CCMG_PASS_WAVES_PER_EU 1
 #endif
 
-template <typename T, int SPHI, int LOAD, int RES, int M, int WY>
+#ifndef CCMG_PARENTS_PER_PLANE
+#define CCMG_PARENTS_PER_PLANE 0
+#endif
+constexpr bool kParentsPerPlane = CCMG_PARENTS_PER_PLANE != 0;
+
+template <typename T, int SPHI, int LOAD, int RES, int M, int WY, bool PAD = false>
 __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassParams<T> P)
 {
     using Sh = PassShape<T, SPHI, RES, M, WY, LOAD>;
@@ -491,8 +496,11 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     unsigned offE[NE];
 #pragma unroll
     for (int r = 0; r < M; r += (YP ? 1 : 2)) offE[YP ? r : r / 2] = coarse_off(r, vrow[r]);
-    auto load_parents = [&](int t, T* e) {
-        const bool zin = (t >= 0) && (t < nz);
+    // PAD: planes at or beyond `tlim` are not needed; their loads read zeros
+    // through a size-0 descriptor (no branch, so no register joins that would
+    // make the compiler wait for loads still in flight)
+    auto load_parents = [&](int t, T* e, int tlim) {
+        const bool zin = (t >= 0) && (t < nz) && (!PAD || t < tlim);
         const auto re = plane_rsrc(P.ec, cplaneB, t >> 1, zin);
 #pragma unroll
         for (int i = 0; i < NE; ++i) bload1(re, offE[i], e[i]);
@@ -503,8 +511,8 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     T elast[NE];
 #pragma unroll
     for (int i = 0; i < NE; ++i) elast[i] = T(0);
-    auto load_plane = [&](int t, int k, auto oddt) {
-        const bool zin = (t >= 0) && (t < nz);
+    auto load_plane = [&](int t, int k, auto oddt, int tlim) {
+        const bool zin = (t >= 0) && (t < nz) && (!PAD || t < tlim);
         const auto rb = plane_rsrc(P.b, planeB, t, zin);
         // a null phi_in reads as zero (the zero initial guess: no load is made)
         const auto rp = plane_rsrc(P.phi_in, planeB, t, zin && LOAD != LOAD_ZERO && P.phi_in != nullptr);
@@ -516,7 +524,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
             else { nph[k][r][0] = T(0); nph[k][r][1] = T(0); }
             if constexpr (LOAD == LOAD_CORR) bload2(rc, offL4[r], ncr[k][r][0], ncr[k][r][1]);
         }
-        if constexpr (LOAD == LOAD_PROLONG && !decltype(oddt)::value) load_parents(t, nex[k]);
+        if constexpr (LOAD == LOAD_PROLONG && (kParentsPerPlane || !decltype(oddt)::value)) load_parents(t, nex[k], tlim);
     };
 
     // tbeg has the parity of S (z0 is even); a cross-strip restriction
@@ -525,22 +533,31 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     T q1p = T(0);                                   // row-1 pair sum of the previous step's plane
 #pragma unroll
     for (int k = 0; k < PD; ++k) {
-        if ((S + k) & 1) load_plane(tbeg + k, k, std::true_type{});
-        else load_plane(tbeg + k, k, std::false_type{});
+        if ((S + k) & 1) load_plane(tbeg + k, k, std::true_type{}, tend);
+        else load_plane(tbeg + k, k, std::false_type{}, tend);
     }
     // the first plane is odd when S is: its parents are those of plane tbeg - 1
-    if constexpr (LOAD == LOAD_PROLONG && (S & 1)) load_parents(tbeg - 1, elast);
+    if constexpr (LOAD == LOAD_PROLONG && (S & 1) && !kParentsPerPlane) load_parents(tbeg - 1, elast, tend);
 
-    for (int tb = tbeg; tb < tend; tb += U) {
+    // PAD: the march runs a whole number of unrolled blocks of U steps; the
+    // steps past tend load zeros (size-0 descriptors) and find every stage,
+    // output, residual and restriction outside its z range, so they only move
+    // the rings and pass the barrier.  Without it every step tests t < tend,
+    // which joins every ring register after every step; the compiler's
+    // copies at those joins wait for the prefetched planes, so a long march
+    // loses its prefetch (the finest post-smoothing pass ran 10 % slower),
+    // while a short one (coarse levels) would lose more to the padding.
+    const int tstop = PAD ? tbeg + U * ((tend - tbeg + U - 1) / U) : tend;
+    for (int tb = tbeg; tb < tstop; tb += U) {
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int t = tb + q;
-            if (t < tend) {
+            if (PAD || t < tend) {
                 const int par = t & 1;
                 // ---- stage 0: the prefetched plane t enters the rings; plane t+PD is requested
                 {
                     const int s0 = q % RP, sb0 = q % RB, k = q % PD;
-                    if constexpr (LOAD == LOAD_PROLONG) {
+                    if constexpr (LOAD == LOAD_PROLONG && !kParentsPerPlane) {
                         if (((S + q) & 1) == 0) {
 #pragma unroll
                             for (int i = 0; i < NE; ++i) elast[i] = nex[k][i];
@@ -550,8 +567,9 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     for (int r = 0; r < M; ++r) {
                         T v0 = nph[k][r][0], v1 = nph[k][r][1];
                         if constexpr (LOAD == LOAD_PROLONG) {
-                            v0 += P.omega * elast[YP ? r : r / 2];
-                            v1 += P.omega * elast[YP ? r : r / 2];
+                            const T e = kParentsPerPlane ? nex[k][YP ? r : r / 2] : elast[YP ? r : r / 2];
+                            v0 += P.omega * e;
+                            v1 += P.omega * e;
                         }
                         if constexpr (LOAD == LOAD_CORR) {
                             v0 += sig_cur * (T)ncr[k][r][0];
@@ -560,9 +578,17 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                         ph[s0][r][0] = v0; ph[s0][r][1] = v1;
                         bb[sb0][r][0] = nbb[k][r][0]; bb[sb0][r][1] = nbb[k][r][1];
                     }
-                    if (t + PD < tend) {
-                        if ((S + q + PD) & 1) load_plane(t + PD, k, std::true_type{});
-                        else load_plane(t + PD, k, std::false_type{});
+                    if constexpr (PAD) {
+                        // the slot's old contents are consumed above: issue its next loads
+                        // only now, so that they reuse the slot's registers (a load hoisted
+                        // above those uses would land in other registers, and the copies
+                        // back into the slot would wait for it); planes past tend read zeros
+                        __builtin_amdgcn_sched_barrier(0);
+                        if ((S + q + PD) & 1) load_plane(t + PD, k, std::true_type{}, tend);
+                        else load_plane(t + PD, k, std::false_type{}, tend);
+                    } else if (t + PD < tend) {
+                        if ((S + q + PD) & 1) load_plane(t + PD, k, std::true_type{}, tend);
+                        else load_plane(t + PD, k, std::false_type{}, tend);
                     }
                     const int ppar = (S + q) & 1;
                     if constexpr (SPHI > 0) {
