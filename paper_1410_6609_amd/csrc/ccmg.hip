@@ -196,6 +196,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 int g_num_cus = 256;   // set from the device at workspace attachment
 constexpr size_t kBottomMaxLds = 160 * 1024;
 constexpr int kPadMinPlanes = 64;   // z-chunks from which FP64 passes march whole unrolled blocks
+constexpr int kFoldMaxBlocks = 4096;   // grid of the fold (grid-stride over x-rows)
 
 template <typename T, int SPHI, int LOAD, int RES>
 bool launch_one(const PassParams<T>& P0, hipStream_t st)
@@ -553,7 +554,6 @@ int enqueue_ctl_init(ccmg_solver* s, double rtol)
     return CCMG_OK;
 }
 
-// b-tilde_0 = h^2 (f + boundary terms); homogeneous=true drops the boundary values
 // ---- variable permittivity -----------------------------------------------
 VcLevel vc_level(const ccmg_solver* s, int l)
 {
@@ -747,7 +747,11 @@ int enqueue_vc_cycle(ccmg_solver* s, double* phi0, int fin_cycle, bool l0_zero =
     return CCMG_OK;
 }
 
-int enqueue_fold(ccmg_solver* s, const double* f, bool homogeneous)
+// b-tilde_0 = h^2 (f + boundary terms); homogeneous=true drops the boundary
+// values.  With init_norm (constant coefficients only) the same kernel also
+// reduces ||b-tilde|| and finalises it as the initial residual of the zero
+// guess (FIN_INIT), in place of a norm pass over b-tilde.
+int enqueue_fold(ccmg_solver* s, const double* f, bool homogeneous, bool init_norm = false)
 {
     if (s->vc_on) return enqueue_vc_fold(s, f, homogeneous);
     const LevelBuf& B = s->lv[0];
@@ -765,7 +769,16 @@ int enqueue_fold(ccmg_solver* s, const double* f, bool homogeneous)
         P.face[fc] = (!homogeneous && s->face_on[fc]) ? s->face_vals[fc] : nullptr;
         P.dirichlet[fc] = s->bc[fc].kind == CCMG_DIRICHLET;
     }
-    hipLaunchKernelGGL(k_fold, dim3(grid1d(B.n)), dim3(256), 0, s->stream, P);
+    const int rows = B.ny * B.nz;
+    if (init_norm) {
+        const int nb = std::max(1, std::min({rows, s->max_partials, kFoldMaxBlocks}));
+        hipLaunchKernelGGL(k_fold<true>, dim3(nb), dim3(kFoldThreads), 0, s->stream, P, s->partials);
+        hipLaunchKernelGGL(k_finish_norm<512>, dim3(1), dim3(512), 0, s->stream, (const double*)s->partials, nb, s->ctl,
+                           (int)FIN_INIT, 0, 0);
+    } else {
+        hipLaunchKernelGGL(k_fold<false>, dim3(std::min(rows, kFoldMaxBlocks)), dim3(kFoldThreads), 0, s->stream, P,
+                           (double*)nullptr);
+    }
     LAUNCHCHK(s);
     return CCMG_OK;
 }
@@ -881,8 +894,10 @@ int finish_stats(ccmg_solver* s, const CtlHead& h, int inner_per_step, ccmg_stat
 
 // Whole solve on b-tilde_0 already in the workspace.  phi: initial guess in,
 // solution out; with zero_guess the guess is phi = 0 and phi is output only.
+// init_done: the fold already finalised the initial norm (zero guess,
+// constant coefficients).
 int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_stats* st,
-                 std::chrono::steady_clock::time_point t0, bool zero_guess = false)
+                 std::chrono::steady_clock::time_point t0, bool zero_guess = false, bool init_done = false)
 {
     const LevelBuf& B0 = s->lv[0];
     // From the zero guess phi is never loaded before it is first written
@@ -893,7 +908,7 @@ int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_
     const bool no_load = zero_guess && !(s->vc_on && s->periodic);
     int rc;
     if (no_load) {
-        if ((rc = enqueue_norm(s, nullptr, FIN_INIT, RES_NORM, nullptr, nullptr, 0))) return rc;
+        if (!init_done && (rc = enqueue_norm(s, nullptr, FIN_INIT, RES_NORM, nullptr, nullptr, 0))) return rc;
         if (max_cycles == 0)   // no cycle will write phi: the last iterate is the guess
             hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(B0.n)), dim3(256), 0, s->stream, phi, B0.n, 0.0);
         else
@@ -1619,8 +1634,9 @@ int ccmg_solve_zero(ccmg_solver* s, double* d_phi, const double* d_f, double rto
     NEED_DEV(s, d_phi, "d_phi");
     NEED_DEV(s, d_f, "d_f");
     if ((rc = enqueue_ctl_init(s, rtol))) return rc;
-    if ((rc = enqueue_fold(s, d_f, false))) return rc;
-    return solve_folded(s, d_phi, rtol, max_cycles, st, t0, true);
+    const bool fused = !s->vc_on;   // the fold also reduces the initial norm
+    if ((rc = enqueue_fold(s, d_f, false, fused))) return rc;
+    return solve_folded(s, d_phi, rtol, max_cycles, st, t0, true, fused);
 }
 
 int ccmg_solve_zero_static(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, int max_cycles,
@@ -1693,8 +1709,9 @@ int ccmg_adjoint_solve(ccmg_solver* s, const double* d_g, double* d_lambda, int 
     NEED_DEV(s, d_lambda, "d_lambda");
     const size_t n0 = s->lv[0].n;
     if ((rc = enqueue_ctl_init(s, rtol))) return rc;
-    if ((rc = enqueue_fold(s, d_g, true))) return rc;
-    const int src = solve_folded(s, d_lambda, rtol, max_cycles, st, t0, true);   // from lambda = 0
+    const bool fused = !s->vc_on;   // the fold also reduces the initial norm
+    if ((rc = enqueue_fold(s, d_g, true, fused))) return rc;
+    const int src = solve_folded(s, d_lambda, rtol, max_cycles, st, t0, true, fused);   // from lambda = 0
     if (src != CCMG_OK && src != CCMG_E_NOCONV) return src;
     if (d_drho) {
         NEED_DEV(s, d_drho, "d_drho");

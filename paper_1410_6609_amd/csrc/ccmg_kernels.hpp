@@ -1332,24 +1332,37 @@ __device__ __forceinline__ double fold_term(const FoldParams& P, int fc, size_t 
     return P.dirichlet[fc] ? 2.0 * g / (P.h * P.h) : g / P.h;
 }
 
-__global__ void k_fold(FoldParams P)
+// One block per x-row at a time (rows z-major, grid-stride over the nz*ny
+// rows): the row's y and z faces are uniform, so only x needs per-cell tests
+// and no cell index is divided.  NORM: the block also sums b-tilde^2 over its
+// rows and stores it as both norm partials (the residual of the zero guess is
+// b-tilde itself), for k_finish_norm in block order.
+constexpr int kFoldThreads = 256;
+template <bool NORM>
+__global__ __launch_bounds__(kFoldThreads) void k_fold(FoldParams P, double* partials)
 {
 #pragma clang fp contract(off)
     const int nx = P.nx, ny = P.ny, nz = P.nz;
-    const size_t n = (size_t)nx * ny * nz;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx);
-        const int j = (int)((c / nx) % ny);
-        const int k = (int)(c / ((size_t)nx * ny));
-        double v = P.f[c];
-        if (i == 0) v += fold_term(P, 0, (size_t)k * ny + j);
-        if (i == nx - 1) v += fold_term(P, 1, (size_t)k * ny + j);
-        if (j == 0) v += fold_term(P, 2, (size_t)k * nx + i);
-        if (j == ny - 1) v += fold_term(P, 3, (size_t)k * nx + i);
-        if (k == 0) v += fold_term(P, 4, (size_t)j * nx + i);
-        if (k == nz - 1) v += fold_term(P, 5, (size_t)j * nx + i);
-        P.bt[c] = v * P.h2;
+    const int rows = ny * nz;
+    double acc = 0.0;
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int j = row % ny, k = row / ny;
+        const size_t base = (size_t)row * nx;
+        for (int i = threadIdx.x; i < nx; i += kFoldThreads) {
+            const size_t c = base + i;
+            double v = P.f[c];
+            if (i == 0) v += fold_term(P, 0, (size_t)k * ny + j);
+            if (i == nx - 1) v += fold_term(P, 1, (size_t)k * ny + j);
+            if (j == 0) v += fold_term(P, 2, (size_t)k * nx + i);
+            if (j == ny - 1) v += fold_term(P, 3, (size_t)k * nx + i);
+            if (k == 0) v += fold_term(P, 4, (size_t)j * nx + i);
+            if (k == nz - 1) v += fold_term(P, 5, (size_t)j * nx + i);
+            const double bt = v * P.h2;
+            P.bt[c] = bt;
+            if constexpr (NORM) acc += bt * bt;
+        }
     }
+    if constexpr (NORM) store_partials<kFoldThreads>(acc, acc, partials, blockIdx.x);
 }
 
 template <typename T>

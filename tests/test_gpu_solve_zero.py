@@ -1,5 +1,6 @@
 """Solve from the zero initial guess (ccmg_solve_zero, Alg. 1 started from
-phi = 0): the iterates are those of ccmg_solve on a zeroed phi, bit for bit;
+phi = 0): the iterates are those of ccmg_solve on a zeroed phi, bit for bit
+(the relative residuals up to the association of ||b||);
 phi is output only (here filled with NaN beforehand, so a read of it would
 show); and a solve that stops before its first cycle returns phi = 0."""
 import numpy as np
@@ -31,8 +32,10 @@ def test_solve_zero_matches_zeroed_guess(case, precision):
     p1 = nan_field(shape)
     _, st1 = s.solve(f, p1, rtol=1e-10, zero_guess=True)
     assert torch.equal(p0, p1)
-    assert (st0.cycles, st0.inner_cycles, st0.rel_res0, st0.rel_res) == \
-        (st1.cycles, st1.inner_cycles, st1.rel_res0, st1.rel_res)
+    assert (st0.cycles, st0.inner_cycles, st0.rel_res0) == (st1.cycles, st1.inner_cycles, st1.rel_res0)
+    # the zero-guess solve reduces ||b|| in the fold kernel, ccmg_solve in its
+    # first norm pass: the same sum in another association
+    assert abs(st1.rel_res - st0.rel_res) <= 1e-13 * st0.rel_res
     # phi = None takes the same path
     p2, st2 = s.solve(f, rtol=1e-10)
     assert torch.equal(p0, p2) and st2.cycles == st0.cycles
