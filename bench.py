@@ -73,7 +73,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_solver(w: W.Workload, dev, precision=pkg.FP64, fuse=2, inner=3):
+def make_solver(w: W.Workload, dev, precision=pkg.FP64, fuse=2, inner=4):
     opt = pkg.Options(levels=w.levels, nu1=w.nu1, nu2=w.nu2, omega=w.omega, precision=precision,
                       fuse_sweeps=fuse, ir_inner_cycles=inner)
     return pkg.Solver(w.shape, w.h, list(zip(w.kinds, w.values)), opt, device=dev)
@@ -404,7 +404,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ir", action="store_true", help="skip the FP32-IR comparison")
     ap.add_argument("--fuse", type=int, default=2)
-    ap.add_argument("--inner", type=int, default=3)
+    ap.add_argument("--inner", type=int, default=4)
     ap.add_argument("--no-scene", action="store_true", help="skip the time-step scene")
     ap.add_argument("--no-c2", action="store_true", help="skip the 256^3 workload section")
     ap.add_argument("--no-vc", action="store_true", help="skip the variable-permittivity solve")

@@ -81,7 +81,7 @@ typedef struct {
     int levels;           /* hierarchy depth; 0 = coarsen while the dims stay even and the grid exceeds 512 cells */
     double omega;         /* coarse-correction factor (default 2.0; Sec. 3 "about 2") */
     int precision;        /* CCMG_FP64 or CCMG_FP32_IR */
-    int ir_inner_cycles;  /* FP32 V-cycles per refinement step (default 3) */
+    int ir_inner_cycles;  /* FP32 V-cycles per refinement step (default 4) */
     double cg_rtol;       /* coarsest-grid CG: stop at ||r|| <= cg_rtol ||b|| (default 1e-13) */
     int cg_maxit;         /* coarsest-grid CG iteration cap (0 = 2 x coarsest cells) */
     int fuse_sweeps;      /* RB-GS sweeps fused per smoother kernel pass: 1 or 2 (default 2); iterates are identical */

@@ -67,7 +67,7 @@ class Options:
     levels: int = 0
     omega: float = 2.0
     precision: int = FP64
-    ir_inner_cycles: int = 3
+    ir_inner_cycles: int = 4
     cg_rtol: float = 1e-13
     cg_maxit: int = 0
     fuse_sweeps: int = 2

@@ -1194,7 +1194,7 @@ void ccmg_default_options(ccmg_options* o)
     o->levels = 0;
     o->omega = 2.0;
     o->precision = CCMG_FP64;
-    o->ir_inner_cycles = 3;
+    o->ir_inner_cycles = 4;
     o->cg_rtol = 1e-13;
     o->cg_maxit = 0;
     o->fuse_sweeps = 2;

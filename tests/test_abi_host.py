@@ -161,7 +161,7 @@ def test_defaults():
     assert (o.nu1, o.nu2, o.omega, o.precision, o.levels) == (2, 2, 2.0, 0, 0)
     assert o.cg_rtol == 1e-13
     assert (o.fuse_sweeps, o.bottom_cells, o.variable_eps) == (2, 4096, 0)
-    assert o.ir_inner_cycles == 3
+    assert o.ir_inner_cycles == 4
     assert o.ir_cg_rtol == 1e-6
 
 

@@ -20,7 +20,7 @@ def solver(shape, levels, kinds, values, h=None, **opt):
     return pkg.Solver(shape, h, list(zip(kinds, values)), pkg.Options(levels=levels, **opt), device=DEV)
 
 
-@pytest.mark.parametrize("inner", [1, 2, 3])
+@pytest.mark.parametrize("inner", [1, 2, 3, 4])
 @pytest.mark.parametrize("case", CASES, ids=ids)
 def test_fp32_ir_reaches_fp64_accuracy(case, inner):
     shape, levels, kinds, values = case
