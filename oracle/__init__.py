@@ -18,21 +18,26 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = [os.path.join(_HERE, "ccmg_oracle.c"), os.path.join(_HERE, "levelops.inc")]
-LIB_PATH = os.path.join(_HERE, "libccmg_oracle.so")
+# CCMG_ORACLE_LIB names another build of the same sources (the sanitizer run)
+LIB_PATH = os.environ.get("CCMG_ORACLE_LIB") or os.path.join(_HERE, "libccmg_oracle.so")
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
 
 OK, E_ARG, E_NONFINITE, E_NOCONV = 0, -1, -5, -6
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FP contraction, OpenMP)."""
-    if not force and os.path.exists(LIB_PATH):
-        return LIB_PATH
-    tmp = LIB_PATH + ".tmp"
+def build(force: bool = True, out: Optional[str] = None, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (no FP contraction, OpenMP).  sanitize: with
+    AddressSanitizer and UndefinedBehaviorSanitizer (UB aborts), into `out`."""
+    out = out or LIB_PATH
+    if not force and os.path.exists(out):
+        return out
+    tmp = out + ".tmp"
     cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-shared", "-fPIC", "-Wall", "-Wno-unknown-pragmas", "-Wno-unused-function", "-o", tmp, _SRC[0], "-lm"]
+           "-shared", "-fPIC", "-Wall", "-Wno-unknown-pragmas", "-Wno-unused-function",
+           *(SANITIZE_FLAGS if sanitize else []), "-o", tmp, _SRC[0], "-lm"]
     subprocess.run(cmd, check=True, cwd=_HERE)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 _lib = None

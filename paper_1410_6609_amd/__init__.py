@@ -33,7 +33,8 @@ _ERR_NAMES = {E_ARG: "E_ARG", E_DIMS: "E_DIMS", E_SINGULAR: "E_SINGULAR", E_HIP:
               E_NONFINITE: "E_NONFINITE", E_NOCONV: "E_NOCONV", E_STATE: "E_STATE"}
 MAX_CYCLES = 1000
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libccmg.so")
+# CCMG_LIB names another build of the same sources (the host-sanitizer run)
+LIB_PATH = os.environ.get("CCMG_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libccmg.so")
 
 
 class CcmgError(RuntimeError):

@@ -28,10 +28,18 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+# host code only (the device code is built as usual): AddressSanitizer and
+# UndefinedBehaviorSanitizer, UB aborting
+HOST_SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                       "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+                       "-shared-libsan"]
+
+
+def build(verbose: bool = False, out: str = LIB, defines=(), sanitize_host: bool = False) -> str:
     """Compile libccmg.so; `defines` are extra -D tuning macros (tile shape)."""
     tmp = out + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *[f"-D{d}" for d in defines], "-o", tmp, SRC]
+    cmd = [hipcc(), *HIPCC_FLAGS, *[f"-D{d}" for d in defines], *(HOST_SANITIZE_FLAGS if sanitize_host else []),
+           "-o", tmp, SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=HERE)
