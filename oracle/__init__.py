@@ -84,6 +84,12 @@ def lib() -> ctypes.CDLL:
                                     dp, dp, dp], None),
             "or_solve": ([I, I, I, D, ip, I, I, I, D, D, I, dp, dp, D, I, dp, ip], I),
             "or_solve_ir": ([I, I, I, D, ip, I, I, I, D, D, I, I, dp, dp, D, I, dp, ip], I),
+            "or_pb_apply": ([I, I, I, D, I, ip, D, dp, dp], None),
+            "or_pb_rbgs_sweep": ([I, I, I, D, I, ip, D, dp, dp], None),
+            "or_pb_cg": ([I, I, I, D, I, ip, D, dp, dp, D, I], I),
+            "or_pb_solve": ([I, I, I, D, ip, I, I, I, D, D, I, D, dp, dp, D, I, dp, ip], I),
+            "or_pb_nl_residual": ([I, I, I, D, ip, D, dp, dp, dp], None),
+            "or_pb_nl_solve": ([I, I, I, D, ip, I, I, I, D, D, I, D, I, dp, dp, D, I, dp, ip], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -411,3 +417,78 @@ def vc_solve(b, h, kinds, levels, eps, nu1=2, nu2=2, omega=2.0, rtol=1e-10, max_
     if st == E_ARG:
         raise ValueError("oracle: invalid hierarchy")
     return phi, hist[: cyc.value + 1].copy(), st
+
+
+# ---- Poisson-Boltzmann (extension; the equation and iteration are the reading
+# written in ccmg_oracle.c) ---------------------------------------------------
+
+def pb_apply(phi, h, kinds, k2, level: int = 0) -> np.ndarray:
+    """(A_l + k2 I) phi: the linearised Poisson-Boltzmann operator."""
+    phi = _f64(phi)
+    out = np.empty_like(phi)
+    nx, ny, nz = _shape(phi)
+    lib().or_pb_apply(nx, ny, nz, h, level, _kinds(kinds), float(k2), _dp(phi), _dp(out))
+    return out
+
+
+def pb_rbgs_sweep(phi, b, h, kinds, k2, level: int = 0, sweeps: int = 1) -> np.ndarray:
+    phi = _f64(phi).copy()
+    b = _f64(b)
+    nx, ny, nz = _shape(phi)
+    for _ in range(sweeps):
+        lib().or_pb_rbgs_sweep(nx, ny, nz, h, level, _kinds(kinds), float(k2), _dp(phi), _dp(b))
+    return phi
+
+
+def pb_cg(b, h, kinds, k2, level: int = 0, rtol: float = 1e-13, maxit: Optional[int] = None):
+    b = _f64(b)
+    x = np.zeros_like(b)
+    nx, ny, nz = _shape(b)
+    maxit = 2 * b.size if maxit is None else maxit
+    it = lib().or_pb_cg(nx, ny, nz, h, level, _kinds(kinds), float(k2), _dp(b), _dp(x), rtol, maxit)
+    return x, it
+
+
+def pb_solve(b, h, kinds, levels, k2, nu1=2, nu2=2, omega=2.0, rtol=1e-10, max_cycles=100,
+             phi0=None, cg_rtol=1e-13, cg_maxit=None):
+    """Linear (Debye-Hueckel) Poisson-Boltzmann multigrid on the folded RHS b.
+    Returns (phi, history, status)."""
+    b = _f64(b)
+    phi = np.zeros_like(b) if phi0 is None else _f64(phi0).copy()
+    nx, ny, nz = _shape(b)
+    hist = np.zeros(max_cycles + 1)
+    cyc = ctypes.c_int(0)
+    cg_maxit = default_cg_maxit((nx, ny, nz), levels) if cg_maxit is None else cg_maxit
+    st = lib().or_pb_solve(nx, ny, nz, h, _kinds(kinds), levels, nu1, nu2, omega, cg_rtol, cg_maxit,
+                           float(k2), _dp(b), _dp(phi), rtol, max_cycles, _dp(hist), ctypes.byref(cyc))
+    if st == E_ARG:
+        raise ValueError("oracle: invalid hierarchy")
+    return phi, hist[: cyc.value + 1].copy(), st
+
+
+def pb_nl_residual(psi, b, h, kinds, k2) -> np.ndarray:
+    """b - A psi - k2 sinh(psi) on the finest level."""
+    psi, b = _f64(psi), _f64(b)
+    r = np.empty_like(psi)
+    nx, ny, nz = _shape(psi)
+    lib().or_pb_nl_residual(nx, ny, nz, h, _kinds(kinds), float(k2), _dp(psi), _dp(b), _dp(r))
+    return r
+
+
+def pb_nl_solve(b, h, kinds, levels, k2, inner=2, nu1=2, nu2=2, omega=2.0, rtol=1e-10, max_outer=200,
+                psi0=None, cg_rtol=1e-13, cg_maxit=None):
+    """Nonlinear Poisson-Boltzmann -Lap(psi) + k2 sinh(psi) = f on the folded RHS b
+    by the shifted chord iteration (inner linear V-cycles per step).  Returns
+    (psi, history, status)."""
+    b = _f64(b)
+    psi = np.zeros_like(b) if psi0 is None else _f64(psi0).copy()
+    nx, ny, nz = _shape(b)
+    hist = np.zeros(max_outer + 1)
+    cyc = ctypes.c_int(0)
+    cg_maxit = default_cg_maxit((nx, ny, nz), levels) if cg_maxit is None else cg_maxit
+    st = lib().or_pb_nl_solve(nx, ny, nz, h, _kinds(kinds), levels, nu1, nu2, omega, cg_rtol, cg_maxit,
+                              float(k2), int(inner), _dp(b), _dp(psi), rtol, max_outer, _dp(hist),
+                              ctypes.byref(cyc))
+    if st == E_ARG:
+        raise ValueError("oracle: invalid hierarchy")
+    return psi, hist[: cyc.value + 1].copy(), st

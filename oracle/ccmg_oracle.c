@@ -67,6 +67,8 @@ typedef struct {
     int nx, ny, nz;
     double s;      /* operator scale 1/(2^l h0^2) */
     int kind[6];   /* x-, x+, y-, y+, z-, z+ */
+    double k2;     /* reaction coefficient kappa^2 of the linearised Poisson-Boltzmann
+                      operator (0: Poisson); the same on every level, see below */
 } or_level;
 
 #define IDX(L, i, j, k) ((((size_t)(k)) * (size_t)(L)->ny + (size_t)(j)) * (size_t)(L)->nx + (size_t)(i))
@@ -96,6 +98,7 @@ static or_level make_level(int nx, int ny, int nz, double h, int level, const in
     L.nx = nx; L.ny = ny; L.nz = nz;
     L.s = 1.0 / (ldexp(1.0, level) * h * h);
     for (int f = 0; f < 6; ++f) L.kind[f] = kinds[f];
+    L.k2 = 0.0;
     return L;
 }
 
@@ -1225,5 +1228,156 @@ int or_vc_solve(int nx, int ny, int nz, double h, const int* kinds, int levels, 
         if (l > 0) { free(ph[l]); free(bb[l]); }
         free(rr[l]);
     }
+    return status;
+}
+
+/* ====================== Poisson-Boltzmann (extension) =========================
+ * The paper's outlook names the Poisson-Boltzmann equation (charged particles in
+ * an electrolyte, with double layers) as a further equation for this solver and
+ * its boundary treatment (Sec. 9), without writing it out.  Reading taken: a
+ * symmetric electrolyte in dimensionless potential psi (e psi / k_B T for a
+ * monovalent salt) and inverse Debye length kappa,
+ *     -Lap(psi) + kappa^2 sinh(psi) = f,
+ * with the reaction term taken at the cell centre (midpoint rule of the finite
+ * volume), the same stencil and boundary folding as Poisson's equation, and the
+ * linearised (Debye-Hueckel) operator -Lap + kappa^2 as its small-potential
+ * limit.  Coarse operators: 2^l times the operator rediscretised at spacing
+ * 2^l h, A_l + 2^l kappa^2 I.  For the Laplacian part this is the Galerkin
+ * product of Sec. 3 (the reason for the correction factor about 2); with
+ * omega = 2 the cycle is then the rediscretised cycle with omega = 1 for the
+ * whole operator.  (The Galerkin product of the reaction term alone would be
+ * kappa^2 I on every level, R P = I; with omega = 2 it over-corrects the smooth
+ * modes that the reaction term dominates.)  The nonlinear equation is solved
+ * by a shifted chord iteration with the linear multigrid as inner solver:
+ *     r_k = b - A psi_k - kappa^2 sinh(psi_k),   c_k = cosh(max |psi_k|),
+ *     (A + c_k kappa^2 I) delta = r_k  by `inner` V-cycles from delta = 0,
+ *     psi_{k+1} = psi_k + delta,
+ * while ||r_k|| / ||b|| >= rtol.  With c_k >= cosh(psi) everywhere on the
+ * segment between iterate and solution the error map is a contraction, so the
+ * iteration converges for any potential; for |psi| <~ 1 it is Newton's method
+ * up to the variation of cosh. */
+
+static void hier_set_k2(or_hier* H, double k2)
+{
+    for (int l = 0; l < H->nlev; ++l) H->lev[l].k2 = ldexp(k2, l);
+}
+
+void or_pb_apply(int nx, int ny, int nz, double h, int level, const int* kinds, double k2,
+                 const double* phi, double* out)
+{
+    or_level L = make_level(nx, ny, nz, h, level, kinds);
+    L.k2 = k2;
+    apply_d(&L, phi, out);
+}
+
+void or_pb_rbgs_sweep(int nx, int ny, int nz, double h, int level, const int* kinds, double k2,
+                      double* phi, const double* b)
+{
+    or_level L = make_level(nx, ny, nz, h, level, kinds);
+    L.k2 = k2;
+    rbgs_sweep_d(&L, phi, b);
+}
+
+int or_pb_cg(int nx, int ny, int nz, double h, int level, const int* kinds, double k2,
+             const double* b, double* x, double rtol, int maxit)
+{
+    or_level L = make_level(nx, ny, nz, h, level, kinds);
+    L.k2 = k2;
+    return cg_d(&L, b, x, rtol, maxit);
+}
+
+/* Linear Poisson-Boltzmann (Debye-Hueckel) solve: or_solve with A_l + 2^l k2 I
+ * on level l. */
+int or_pb_solve(int nx, int ny, int nz, double h, const int* kinds, int levels, int nu1, int nu2,
+                double omega, double cg_rtol, int cg_maxit, double k2, const double* b, double* phi,
+                double rtol, int max_cycles, double* hist, int* cycles_out)
+{
+    or_hier H;
+    if (hier_init(&H, nx, ny, nz, h, kinds, levels, nu1, nu2, omega, cg_rtol, cg_maxit, 0))
+        return OR_E_ARG;
+    hier_set_k2(&H, k2);
+    const or_level* L0 = &H.lev[0];
+    const size_t n = or_cells(L0);
+    H.phi[0] = phi;
+    H.b[0] = (double*)b;
+    const double bnorm = norm2_d(n, b);
+    int k = 0, status = OR_OK;
+    if (bnorm == 0.0) {
+        memset(phi, 0, n * sizeof(double));
+        if (hist) hist[0] = 0.0;
+    } else {
+        residual_d(L0, phi, b, H.r[0]);
+        double rho = norm2_d(n, H.r[0]) / bnorm;
+        if (hist) hist[0] = rho;
+        while (isfinite(rho) && rho >= rtol && k < max_cycles) {
+            vcycle_d(&H, 0);
+            ++k;
+            residual_d(L0, phi, b, H.r[0]);
+            rho = norm2_d(n, H.r[0]) / bnorm;
+            if (hist) hist[k] = rho;
+        }
+        if (!isfinite(rho)) status = OR_E_NONFINITE;
+        else if (rho >= rtol) status = OR_E_NOCONV;
+    }
+    if (cycles_out) *cycles_out = k;
+    H.phi[0] = NULL; H.b[0] = NULL;
+    hier_free(&H);
+    return status;
+}
+
+/* r = b - A psi - k2 sinh(psi) on level 0 (the nonlinear residual). */
+void or_pb_nl_residual(int nx, int ny, int nz, double h, const int* kinds, double k2, const double* psi,
+                       const double* b, double* r)
+{
+    or_level L = make_level(nx, ny, nz, h, 0, kinds);
+    residual_d(&L, psi, b, r);
+    const size_t n = or_cells(&L);
+    for (size_t c = 0; c < n; ++c) r[c] -= k2 * sinh(psi[c]);
+}
+
+/* Nonlinear Poisson-Boltzmann solve by the shifted chord iteration above.
+ * psi: initial guess in, last iterate out; hist[0..outer] receives the
+ * relative nonlinear residuals.  ||b|| = 0 gives psi = 0 (sinh(0) = 0). */
+int or_pb_nl_solve(int nx, int ny, int nz, double h, const int* kinds, int levels, int nu1, int nu2,
+                   double omega, double cg_rtol, int cg_maxit, double k2, int inner, const double* b,
+                   double* psi, double rtol, int max_outer, double* hist, int* outer_out)
+{
+    or_hier H;
+    if (hier_init(&H, nx, ny, nz, h, kinds, levels, nu1, nu2, omega, cg_rtol, cg_maxit, 0))
+        return OR_E_ARG;
+    const or_level* L0 = &H.lev[0];
+    const size_t n = or_cells(L0);
+    double* r = (double*)malloc(n * sizeof(double));
+    double* delta = (double*)malloc(n * sizeof(double));
+    const double bnorm = norm2_d(n, b);
+    int k = 0, status = OR_OK;
+    if (bnorm == 0.0) {
+        memset(psi, 0, n * sizeof(double));
+        if (hist) hist[0] = 0.0;
+    } else {
+        or_pb_nl_residual(nx, ny, nz, h, kinds, k2, psi, b, r);
+        double rho = norm2_d(n, r) / bnorm;
+        if (hist) hist[0] = rho;
+        while (isfinite(rho) && rho >= rtol && k < max_outer) {
+            double m = 0.0;
+            for (size_t c = 0; c < n; ++c) m = fmax(m, fabs(psi[c]));
+            hier_set_k2(&H, k2 * cosh(m));
+            memset(delta, 0, n * sizeof(double));
+            H.phi[0] = delta;
+            H.b[0] = r;
+            for (int i = 0; i < inner; ++i) vcycle_d(&H, 0);
+            for (size_t c = 0; c < n; ++c) psi[c] += delta[c];
+            ++k;
+            or_pb_nl_residual(nx, ny, nz, h, kinds, k2, psi, b, r);
+            rho = norm2_d(n, r) / bnorm;
+            if (hist) hist[k] = rho;
+        }
+        if (!isfinite(rho)) status = OR_E_NONFINITE;
+        else if (rho >= rtol) status = OR_E_NOCONV;
+    }
+    if (outer_out) *outer_out = k;
+    H.phi[0] = NULL; H.b[0] = NULL;
+    hier_free(&H);
+    free(r); free(delta);
     return status;
 }
