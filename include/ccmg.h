@@ -91,6 +91,13 @@ typedef struct {
                              (ccmg_set_permittivity; FP64 only); default 0 */
     double ir_cg_rtol;    /* FP32-IR: coarsest-grid CG tolerance inside the FP32 cycles (default 1e-6:
                              an FP32 correction carries about seven digits; the FP64 cycles use cg_rtol) */
+    double kappa2;        /* Poisson-Boltzmann (the outlook of Sec. 9): kappa^2 >= 0, the squared inverse
+                             Debye length in 1/length^2.  Every linear call (solve, cycles, residual,
+                             smoothing, adjoint, FP32-IR) then uses the linearised (Debye-Hueckel) operator
+                             -Lap + kappa^2 on the finest level, with 2^l-scaled coarse reaction terms (the
+                             operator rediscretised at spacing 2^l h, times 2^l, as the Galerkin product is for
+                             the Laplacian); ccmg_solve_pb solves the nonlinear equation.  Default 0 (Poisson).
+                             Constant coefficients only: not with variable_eps or periodic faces. */
 } ccmg_options;
 
 typedef struct {
@@ -334,6 +341,24 @@ int ccmg_solve_zero_static(ccmg_solver* s, double* d_phi, const double* d_f, dou
 int ccmg_adjoint_solve(ccmg_solver* s, const double* d_g, double* d_lambda, int n,
                        const double* d_centers, const double* d_radii, double eps, double* d_dq,
                        double* d_drho, double rtol, int max_cycles, ccmg_stats* st);
+
+/* Nonlinear Poisson-Boltzmann equation (the outlook of Sec. 9: charged
+ * particles in an electrolyte, with double layers), read as
+ *     -Lap(psi) + kappa^2 sinh(psi) = f
+ * for a symmetric electrolyte in dimensionless potential, kappa^2 the solver's
+ * option (> 0), f and the face conditions as for ccmg_solve (the reaction term
+ * is taken at cell centres).  d_psi holds the initial guess on entry (it is not
+ * zeroed) and the last iterate on return.  Shifted chord iteration: with the
+ * nonlinear residual r = b - A psi - kappa^2 sinh(psi) and c = cosh(max|psi|),
+ * `inner` (1..16) V-cycles from zero on (A + c kappa^2) delta = r, then
+ * psi += delta; the step contracts for any potential (c bounds cosh(psi)),
+ * and for |psi| up to about 1 it is close to Newton's method.  Repeated while
+ * ||r|| / ||b|| >= rtol, at most max_outer steps; the host synchronises once per
+ * step (max|psi| sets c).  FP64 only.  Statistics: cycles = outer steps,
+ * inner_cycles = their V-cycles, rel_res0 / rel_res the relative nonlinear
+ * residuals.  Errors as ccmg_solve; E_STATE if kappa2 = 0. */
+int ccmg_solve_pb(ccmg_solver* s, double* d_psi, const double* d_f, double rtol, int max_outer, int inner,
+                  ccmg_stats* st);
 
 /* Residual of the finest level: d_r (nullable) = b - A phi with b the folded
  * right-hand side of d_f; rel_res_out (nullable) = ||b - A phi|| / ||b||. */

@@ -52,7 +52,7 @@ class _Options(ctypes.Structure):
                 ("omega", ctypes.c_double), ("precision", ctypes.c_int),
                 ("ir_inner_cycles", ctypes.c_int), ("cg_rtol", ctypes.c_double),
                 ("cg_maxit", ctypes.c_int), ("fuse_sweeps", ctypes.c_int), ("bottom_cells", ctypes.c_int),
-                ("variable_eps", ctypes.c_int), ("ir_cg_rtol", ctypes.c_double)]
+                ("variable_eps", ctypes.c_int), ("ir_cg_rtol", ctypes.c_double), ("kappa2", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -75,11 +75,12 @@ class Options:
     bottom_cells: int = 4096
     variable_eps: int = 0
     ir_cg_rtol: float = 1e-6
+    kappa2: float = 0.0   # Poisson-Boltzmann: squared inverse Debye length (0: Poisson)
 
     def _c(self) -> _Options:
         return _Options(self.nu1, self.nu2, self.levels, self.omega, self.precision,
                         self.ir_inner_cycles, self.cg_rtol, self.cg_maxit, self.fuse_sweeps,
-                        self.bottom_cells, self.variable_eps, self.ir_cg_rtol)
+                        self.bottom_cells, self.variable_eps, self.ir_cg_rtol, self.kappa2)
 
 
 @dataclass
@@ -123,6 +124,8 @@ _SIGS = {
     "ccmg_solve": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
     "ccmg_solve_zero": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
     "ccmg_solve_zero_static": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
+    "ccmg_solve_pb": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Stats)],
+                      ctypes.c_int),
     "ccmg_adjoint_solve": ([_VP, _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_double, _VP, _VP,
                             ctypes.c_double, ctypes.c_int, ctypes.POINTER(_Stats)], ctypes.c_int),
     "ccmg_residual": ([_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -409,6 +412,21 @@ class Solver:
         if check:
             self._check(rc)
         return phi, Stats(st.cycles, st.inner_cycles, st.rel_res0, st.rel_res, st.seconds, rc)
+
+    def solve_pb(self, f: torch.Tensor, psi: Optional[torch.Tensor] = None, rtol: float = 1e-10,
+                 max_outer: int = 200, inner: int = 2, check: bool = True):
+        """Nonlinear Poisson-Boltzmann -Lap(psi) + kappa2 sinh(psi) = f (ccmg_solve_pb;
+        the solver's options set kappa2).  psi: initial guess (None: zero), updated
+        in place.  Returns (psi, Stats)."""
+        f = self._field(f, "f")
+        psi = self.zeros() if psi is None else self._field(psi, "psi")
+        st = _Stats()
+        self._bind_stream()
+        rc = lib().ccmg_solve_pb(self._h, _ptr(psi), _ptr(f), float(rtol), int(max_outer), int(inner),
+                                 ctypes.byref(st))
+        if check:
+            self._check(rc)
+        return psi, Stats(st.cycles, st.inner_cycles, st.rel_res0, st.rel_res, st.seconds, rc)
 
     def vcycle(self, phi: torch.Tensor, f: torch.Tensor, norm: bool = True) -> Optional[float]:
         f = self._field(f, "f")

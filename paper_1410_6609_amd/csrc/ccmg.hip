@@ -128,6 +128,12 @@ struct ccmg_solver {
     Ctl* ctl = nullptr;
     double* partials = nullptr;
     int max_partials = 0;
+    // Poisson-Boltzmann: kappa^2, the chord constant of the nonlinear iteration
+    // (1 for the linear operator), and the nonlinear residual and correction
+    double kappa2 = 0.0;
+    double pb_c = 1.0;
+    double* pb_r = nullptr;
+    double* pb_d = nullptr;
     double* face_vals[6] = {};   // per-cell boundary values (workspace)
     bool face_on[6] = {};        // face uses face_vals instead of bc[].value
     // variable permittivity: stored face coefficients per level (workspace)
@@ -290,20 +296,20 @@ bool dispatch<float>(int sphi, int load, int res, const PassParams<float>& P, hi
 }
 
 template <typename T>
-void launch_cg(const T* b, T* x, int nx, int ny, int nz, const int* sh, double rtol, int maxit, Ctl* ctl,
-               hipStream_t st)
+void launch_cg(const T* b, T* x, int nx, int ny, int nz, const int* sh, double shift, double rtol, int maxit,
+               Ctl* ctl, hipStream_t st)
 {
     const int n = nx * ny * nz;
     if (n <= kCgWaveMax) {
         const size_t lds = (size_t)(nx + 2) * (ny + 2) * (nz + 2) * sizeof(double);
         hipLaunchKernelGGL((k_coarse_cg_wave<T>), dim3(1), dim3(64), lds, st, b, x, nx, ny, nz, sh[0], sh[1], sh[2],
-                           sh[3], sh[4], sh[5], rtol, maxit, ctl);
+                           sh[3], sh[4], sh[5], shift, rtol, maxit, ctl);
         return;
     }
     const int npt = cdiv(n, kCgThreads);
 #define CG_CASE(N)                                                                                          \
     hipLaunchKernelGGL((k_coarse_cg<T, N>), dim3(1), dim3(kCgThreads), 0, st, b, x, nx, ny, nz, sh[0], sh[1], \
-                       sh[2], sh[3], sh[4], sh[5], rtol, maxit, ctl)
+                       sh[2], sh[3], sh[4], sh[5], shift, rtol, maxit, ctl)
     if (npt <= 1) CG_CASE(1);
     else if (npt <= 2) CG_CASE(2);
     else if (npt <= 4) CG_CASE(4);
@@ -366,6 +372,16 @@ struct LevelPtrs {
     T* b[CCMG_MAX_LEVELS];
 };
 
+// Diagonal shift of level l in the integer-stencil form (Poisson-Boltzmann):
+// the level operator is s_l (S_l + shift) with s_l = 1/(2^l h^2), and the
+// reaction term of level l is 2^l c kappa^2 (c: chord constant), so
+// shift = 2^l c kappa^2 / s_l = 4^l h^2 c kappa^2: kappa^2 times the square of
+// the level's spacing, the operator rediscretised there.
+double level_shift(const ccmg_solver* s, int l)
+{
+    return s->kappa2 > 0.0 ? std::ldexp(s->kappa2 * s->pb_c * s->h * s->h, 2 * l) : 0.0;
+}
+
 template <typename T>
 PassParams<T> base_params(const ccmg_solver* s, int l)
 {
@@ -379,6 +395,7 @@ PassParams<T> base_params(const ccmg_solver* s, int l)
     P.partials = s->partials;
     P.max_partials = s->max_partials;
     P.omega = (T)s->opt.omega;
+    P.shift = (T)level_shift(s, l);
     return P;
 }
 
@@ -473,6 +490,7 @@ int enqueue_vcycle(ccmg_solver* s, const LevelPtrs<T>& H, bool l0_zero, int fin_
             B.nz[i] = s->lv[lbot + i].nz;
         }
         for (int f = 0; f < 6; ++f) B.sh[f] = s->sh[f];
+        for (int i = 0; i < B.nlev; ++i) B.shift[i] = level_shift(s, lbot + i);
         B.omega = (T)s->opt.omega;
         B.nu1 = s->opt.nu1;
         B.nu2 = s->opt.nu2;
@@ -490,7 +508,8 @@ int enqueue_vcycle(ccmg_solver* s, const LevelPtrs<T>& H, bool l0_zero, int fin_
         // coarsest level alone
         const int l = L - 1;
         const LevelBuf& B = s->lv[l];
-        launch_cg<T>(H.b[l], H.home[l], B.nx, B.ny, B.nz, s->sh, sizeof(T) == 4 ? s->opt.ir_cg_rtol : s->opt.cg_rtol,
+        launch_cg<T>(H.b[l], H.home[l], B.nx, B.ny, B.nz, s->sh, level_shift(s, l),
+                     sizeof(T) == 4 ? s->opt.ir_cg_rtol : s->opt.cg_rtol,
                      s->cg_maxit, s->ctl, st);
     }
     // ascend
@@ -808,6 +827,7 @@ struct CtlHead {
     unsigned reserved;
     int cg_iters;
     int pad[2];
+    double pb_max;
 };
 static_assert(sizeof(CtlHead) == offsetof(Ctl, hist), "control block header layout");
 
@@ -989,6 +1009,11 @@ size_t layout_workspace(ccmg_solver* s, char* base)
     for (int fc = 0; fc < 6; ++fc) {
         double* fv = (double*)take(sizeof(double) * face_cells(s, fc));
         if (base) s->face_vals[fc] = fv;
+    }
+    if (s->kappa2 > 0.0) {
+        double* r = (double*)take(sizeof(double) * s->lv[0].n);
+        double* d = (double*)take(sizeof(double) * s->lv[0].n);
+        if (base) { s->pb_r = r; s->pb_d = d; }
     }
     if (s->opt.variable_eps) {
         for (int l = 0; l < s->L; ++l) {
@@ -1201,6 +1226,7 @@ void ccmg_default_options(ccmg_options* o)
     o->bottom_cells = kBottomMaxCells;
     o->variable_eps = 0;
     o->ir_cg_rtol = 1e-6;
+    o->kappa2 = 0.0;
 }
 
 int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_face bc[6],
@@ -1242,7 +1268,12 @@ int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_
         if (o.precision != CCMG_FP64) return fail(nullptr, CCMG_E_ARG, "periodic faces are solved in FP64 only");
         o.variable_eps = 1;
     }
-    if (!any_dirichlet) return fail(nullptr, CCMG_E_SINGULAR, "all faces Neumann: the operator is singular");
+    if (!(o.kappa2 >= 0.0) || !std::isfinite(o.kappa2)) return fail(nullptr, CCMG_E_ARG, "kappa2 must be finite and >= 0");
+    if (o.kappa2 > 0.0 && o.variable_eps)
+        return fail(nullptr, CCMG_E_ARG, "the Poisson-Boltzmann term needs constant coefficients (no variable "
+                                         "permittivity or periodic faces)");
+    if (!any_dirichlet && !(o.kappa2 > 0.0))
+        return fail(nullptr, CCMG_E_SINGULAR, "all faces Neumann: the operator is singular");
     // hierarchy depth
     int L = o.levels;
     if (L == 0) {
@@ -1274,6 +1305,7 @@ int ccmg_create(ccmg_solver** out, int nx, int ny, int nz, double h, const ccmg_
         s->sh[f] = bc[f].kind == CCMG_DIRICHLET ? 1 : -1;
     }
     s->opt = o;
+    s->kappa2 = o.kappa2;
     s->periodic = any_periodic;
     s->opt.levels = L;
     s->stream = (hipStream_t)hip_stream;
@@ -1691,6 +1723,64 @@ int ccmg_solve(ccmg_solver* s, double* d_phi, const double* d_f, double rtol, in
     if ((rc = enqueue_ctl_init(s, rtol))) return rc;
     if ((rc = enqueue_fold(s, d_f, false))) return rc;
     return solve_folded(s, d_phi, rtol, max_cycles, st, t0);
+}
+
+int ccmg_solve_pb(ccmg_solver* s, double* d_psi, const double* d_f, double rtol, int max_outer, int inner,
+                  ccmg_stats* st)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = check_ready(s);
+    if (rc) return rc;
+    s->err.clear();
+    if (!(s->kappa2 > 0.0)) return fail(s, CCMG_E_STATE, "solver created without kappa2 > 0");
+    if (s->opt.precision != CCMG_FP64) return fail(s, CCMG_E_ARG, "the Poisson-Boltzmann iteration runs in FP64");
+    if (max_outer < 0 || max_outer > CCMG_MAX_CYCLES) return fail(s, CCMG_E_ARG, "max_outer out of range");
+    if (inner < 1 || inner > 16) return fail(s, CCMG_E_ARG, "inner must be in 1..16");
+    if (!(rtol >= 0.0)) return fail(s, CCMG_E_ARG, "rtol must be >= 0");
+    NEED_DEV(s, d_psi, "d_psi");
+    NEED_DEV(s, d_f, "d_f");
+    const LevelBuf& B0 = s->lv[0];
+    if ((rc = enqueue_ctl_init(s, rtol))) return rc;
+    if ((rc = enqueue_fold(s, d_f, false))) return rc;
+    PbParams P{};
+    P.psi = d_psi;
+    P.bt = B0.b;
+    P.r = s->pb_r;
+    P.nx = B0.nx;
+    P.ny = B0.ny;
+    P.nz = B0.nz;
+    for (int f = 0; f < 6; ++f) P.sh[f] = s->sh[f];
+    P.hk2 = s->h * s->h * s->kappa2;
+    P.partials = s->partials;
+    const int nb = std::max(1, std::min({B0.ny * B0.nz, 2 * s->max_partials / 3, kFoldMaxBlocks}));
+    // the correction equation: right-hand side the nonlinear residual, unknown
+    // delta (level 0), the other levels as for a cycle
+    LevelPtrs<double> H = fp64_ptrs(s, s->pb_d);
+    H.b[0] = s->pb_r;
+    CtlHead h;
+    for (int k = 0;; ++k) {
+        hipLaunchKernelGGL(k_pb_residual, dim3(nb), dim3(kPbThreads), 0, s->stream, P);
+        hipLaunchKernelGGL(k_pb_finish<512>, dim3(1), dim3(512), 0, s->stream, (const double*)s->partials, nb, s->ctl,
+                           k);
+        LAUNCHCHK(s);
+        if ((rc = read_ctl(s, h, -1))) return rc;
+        if (h.done || k >= max_outer) break;
+        // shifted chord step: (A + cosh(max|psi|) kappa^2 I) delta = r by V-cycles from zero
+        s->pb_c = std::cosh(h.pb_max);
+        for (int m = 0; m < inner; ++m) {
+            rc = enqueue_vcycle<double>(s, H, m == 0, 0);
+            if (rc) { s->pb_c = 1.0; return rc; }
+        }
+        s->pb_c = 1.0;
+        hipLaunchKernelGGL(k_axpy, dim3(grid1d(B0.n)), dim3(256), 0, s->stream, d_psi, (const double*)s->pb_d, B0.n);
+        LAUNCHCHK(s);
+    }
+    if (h.bzero) {
+        hipLaunchKernelGGL((k_fill<double>), dim3(grid1d(B0.n)), dim3(256), 0, s->stream, d_psi, B0.n, 0.0);
+        LAUNCHCHK(s);
+    }
+    if ((rc = read_all(s, h))) return rc;
+    return finish_stats(s, h, inner, st, t0);
 }
 
 int ccmg_adjoint_solve(ccmg_solver* s, const double* d_g, double* d_lambda, int n, const double* d_centers,

@@ -47,6 +47,7 @@ struct Ctl {
     unsigned int reserved;  // unused (keeps the layout)
     int cg_iters;       // iterations of the last coarsest-grid CG
     int pad[2];
+    double pb_max;      // Poisson-Boltzmann: max |psi| of the iterate whose residual was reduced last
     double hist[kMaxHist];
 };
 
@@ -76,6 +77,7 @@ struct PassParams {
     int zc;              // planes per block (even)
     int tiles_x, tiles_y, zchunks;
     int sh[6];           // per-face centre shift: +1 Dirichlet, -1 Neumann
+    T shift;             // diagonal shift of the level (linearised Poisson-Boltzmann term), 0 for Poisson
 };
 
 // ---------------------------------------------------------------------------
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
             if (y == ny - 1) d += P.sh[3];
             dxy[r][c] = d;
             // cells outside the domain get 1/d = 0: their update is exactly 0, no select needed
-            inv0[r][c] = vrow[r] ? T(1) / T(d) : T(0);
+            inv0[r][c] = vrow[r] ? T(1) / (T(d) + P.shift) : T(0);
         }
     }
     const int cnx = nx >> 1, cny = ny >> 1;
@@ -652,7 +654,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
 #pragma unroll
                         for (int r = 0; r < M; ++r) {
                             const int o = (cs + r + ppar + YP) & 1;
-                            invz[r] = vrow[r] ? T(1) / T(dxy[r][o] + dz) : T(0);
+                            invz[r] = vrow[r] ? T(1) / (T(dxy[r][o] + dz) + P.shift) : T(0);
                         }
                     }
 #pragma unroll
@@ -731,7 +733,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                             const T ym = r > 0 ? ph[sc][r - 1][c] : elo[c];
                             const T yp = r < M - 1 ? ph[sc][r + 1][c] : ehi[c];
                             const T sum = ((((xm + xq) + ym) + yp) + ph[sm][r][c]) + ph[sp][r][c];
-                            res[r][c] = bb[sb][r][c] - (T(dxy[r][c] + dz) * ph[sc][r][c] - sum);
+                            res[r][c] = bb[sb][r][c] - ((T(dxy[r][c] + dz) + P.shift) * ph[sc][r][c] - sum);
                         }
                     }
                     if constexpr (Sh::XSTRIP_RESTRICT) {
@@ -783,15 +785,15 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
 
 // ---------------------------------------------------------------------------
 // Coarsest level: conjugate gradients in FP64 by one workgroup (Sec. 5.3),
-// search direction resident in LDS.  Solves S x = b-tilde from x = 0 until
-// ||r|| <= rtol ||b|| or maxit, and writes x (as T).
+// search direction resident in LDS.  Solves (S + shift) x = b-tilde from x = 0
+// until ||r|| <= rtol ||b|| or maxit, and writes x (as T).
 // ---------------------------------------------------------------------------
 constexpr int kCgThreads = 256;
 
 template <typename T, int NPT>
 __global__ __launch_bounds__(kCgThreads) void k_coarse_cg(const T* b, T* x_out, int nx, int ny, int nz,
                                                           int sh0, int sh1, int sh2, int sh3, int sh4, int sh5,
-                                                          double rtol, int maxit, Ctl* ctl)
+                                                          double shift, double rtol, int maxit, Ctl* ctl)
 {
     if (ctl != nullptr && ctl->done) return;
     __shared__ double pl[kCgThreads * NPT];
@@ -849,7 +851,7 @@ __global__ __launch_bounds__(kCgThreads) void k_coarse_cg(const T* b, T* x_out, 
 #pragma unroll
                 for (int f = 0; f < 6; ++f) s += nb[k][f] >= 0 ? pl[nb[k][f]] : 0.0;
                 const double pc = dg[k] ? pl[c] : 0.0;
-                qv[k] = dg[k] ? (double)dg[k] * pc - s : 0.0;
+                qv[k] = dg[k] ? ((double)dg[k] + shift) * pc - s : 0.0;
                 pq += pc * qv[k];
             }
             pq = block_sum(pq, 1);
@@ -993,8 +995,8 @@ __device__ __forceinline__ void wave_sum2(double& a, double& b)
 constexpr int kCgWaveMax = 512;
 
 template <typename GetB, typename PutX>
-__device__ int cg_one_wave(GetB get_b, PutX put_x, double* rl, int nx, int ny, int nz, const int* sh, double rtol,
-                           int maxit)
+__device__ int cg_one_wave(GetB get_b, PutX put_x, double* rl, int nx, int ny, int nz, const int* sh, double shift,
+                           double rtol, int maxit)
 {
     constexpr int NPT = kCgWaveMax / 64;
     const int lane = threadIdx.x & 63;
@@ -1046,7 +1048,7 @@ __device__ int cg_one_wave(GetB get_b, PutX put_x, double* rl, int nx, int ny, i
         for (int k = 0; k < NPT; ++k) {
             const double sum = ((((nbs[k][0] + nbs[k][1]) + nbs[k][2]) + nbs[k][3]) + nbs[k][4]) + nbs[k][5];
             const double mask = dg[k] ? 1.0 : 0.0;
-            wv[k] = mask * ((double)dg[k] * rv[k] - sum);
+            wv[k] = mask * (((double)dg[k] + shift) * rv[k] - sum);
             delta += rv[k] * wv[k];
         }
         wave_sum2(gamma, delta);
@@ -1086,8 +1088,8 @@ constexpr int kCgPad = 10 * 10 * 10 + 64;   // padded cells of the largest one-w
 // Standalone coarsest-grid CG for n <= 512 cells: one wave.
 template <typename T>
 __global__ __launch_bounds__(64) void k_coarse_cg_wave(const T* b, T* x_out, int nx, int ny, int nz, int sh0,
-                                                       int sh1, int sh2, int sh3, int sh4, int sh5, double rtol,
-                                                       int maxit, Ctl* ctl)
+                                                       int sh1, int sh2, int sh3, int sh4, int sh5, double shift,
+                                                       double rtol, int maxit, Ctl* ctl)
 {
     if (ctl != nullptr && ctl->done) return;
     extern __shared__ double pl[];
@@ -1096,7 +1098,7 @@ __global__ __launch_bounds__(64) void k_coarse_cg_wave(const T* b, T* x_out, int
     for (int c = threadIdx.x; c < np; c += 64) pl[c] = 0.0;
     __syncthreads();
     const int it = cg_one_wave([&](int c) { return b[c]; }, [&](int c, double v) { x_out[c] = (T)v; }, pl, nx, ny,
-                               nz, sh, rtol, maxit);
+                               nz, sh, shift, rtol, maxit);
     if (threadIdx.x == 0 && ctl != nullptr) ctl->cg_iters = it;
 }
 
@@ -1124,6 +1126,7 @@ struct BottomParams {
     int poff[kBottomMaxLevels];   // offsets of the padded phi arrays
     int boff[kBottomMaxLevels];   // offsets of the b-tilde arrays
     int sh[6];
+    double shift[kBottomMaxLevels];   // per-level diagonal shift (Poisson-Boltzmann term), 0 for Poisson
     T omega;
     int nu1, nu2;
     double cg_rtol;
@@ -1148,7 +1151,7 @@ __host__ __device__ inline void bottom_layout(BottomParams<T>& B, int& nphi, int
 // `sweeps` red-black sweeps on one level in LDS; each thread owns fixed cells
 // of each colour, their padded index and diagonal computed once per call.
 template <typename T>
-__device__ void bottom_smooth(T* ph, const T* bt, int nx, int ny, int nz, const int* sh, int sweeps)
+__device__ void bottom_smooth(T* ph, const T* bt, int nx, int ny, int nz, const int* sh, double shift, int sweeps)
 {
     const int hx = nx / 2, half = hx * ny * nz;   // nx even: each colour has half the cells
     const int sy = nx + 2, sz = (nx + 2) * (ny + 2);
@@ -1171,7 +1174,8 @@ __device__ void bottom_smooth(T* ph, const T* bt, int nx, int ny, int nz, const 
 #pragma unroll
     for (int colour = 0; colour < 2; ++colour)
 #pragma unroll
-        for (int u = 0; u < kBottomCpt; ++u) inv[colour][u] = dg[colour][u] ? T(1) / T(dg[colour][u]) : T(0);
+        for (int u = 0; u < kBottomCpt; ++u)
+            inv[colour][u] = dg[colour][u] ? T(1) / (T(dg[colour][u]) + T(shift)) : T(0);
     for (int sw = 0; sw < sweeps; ++sw) {
 #pragma unroll
         for (int colour = 0; colour < 2; ++colour) {
@@ -1231,7 +1235,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomParams<T>
         const int nx = P.nx[l], ny = P.ny[l], nz = P.nz[l];
         T* ph = ph_all + P.poff[l];
         const T* bt = b_all + P.boff[l];
-        bottom_smooth(ph, bt, nx, ny, nz, P.sh, P.nu1);
+        bottom_smooth(ph, bt, nx, ny, nz, P.sh, P.shift[l], P.nu1);
         // b-tilde of level l+1 = 1/4 sum of the children's residuals
         const int cnx = nx / 2, cny = ny / 2, cnz = nz / 2, nc = cnx * cny * cnz;
         const int sy = nx + 2, sz = (nx + 2) * (ny + 2);
@@ -1252,7 +1256,8 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomParams<T>
                         const int c = padded(i, j, k, nx, ny);
                         const T sum =
                             ((((ph[c - 1] + ph[c + 1]) + ph[c - sy]) + ph[c + sy]) + ph[c - sz]) + ph[c + sz];
-                        const T r = bt[(k * ny + j) * nx + i] - (T(cell_diag(i, j, k, nx, ny, nz, P.sh)) * ph[c] - sum);
+                        const T r = bt[(k * ny + j) * nx + i] -
+                                    ((T(cell_diag(i, j, k, nx, ny, nz, P.sh)) + T(P.shift[l])) * ph[c] - sum);
                         pair = di == 0 ? r : pair + r;
                     }
                     acc[dk][dj] = pair;
@@ -1274,7 +1279,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomParams<T>
                 split3(c, dx, dy, i, j, k);
                 ph[padded(i, j, k, nx, ny)] = (T)v;
             },
-            pl, nx, ny, P.nz[lc], P.sh, P.cg_rtol, P.cg_maxit);
+            pl, nx, ny, P.nz[lc], P.sh, P.shift[lc], P.cg_rtol, P.cg_maxit);
         if (threadIdx.x == 0 && P.ctl != nullptr) P.ctl->cg_iters = it;
     }
     __syncthreads();
@@ -1291,7 +1296,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomParams<T>
             ph[padded(i, j, k, nx, ny)] += P.omega * pc[padded(i >> 1, j >> 1, k >> 1, cnx, cny)];
         }
         __syncthreads();
-        bottom_smooth(ph, b_all + P.boff[l], nx, ny, nz, P.sh, P.nu2);
+        bottom_smooth(ph, b_all + P.boff[l], nx, ny, nz, P.sh, P.shift[l], P.nu2);
     }
     {
         const int nx = P.nx[0], ny = P.ny[0];
@@ -1420,6 +1425,118 @@ __global__ void k_ctl_init(Ctl* ctl, double rtol)
         ctl->reserved = 0u;
         ctl->cg_iters = 0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Poisson-Boltzmann (extension; the outlook of Sec. 9 names the equation for
+// charged particles in an electrolyte, with double layers, without writing it
+// out).  In the b-tilde scale of the finest level the nonlinear equation
+// -Lap(psi) + kappa^2 sinh(psi) = f reads S psi + h^2 kappa^2 sinh(psi) = b-tilde.
+// k_pb_residual: r = b-tilde - S psi - h^2 kappa^2 sinh(psi) by x-rows, with
+// per-block partials (sum r^2, sum b-tilde^2, max |psi|) for k_pb_finish.
+// ---------------------------------------------------------------------------
+constexpr int kPbThreads = 256;
+
+struct PbParams {
+    const double* psi;
+    const double* bt;
+    double* r;
+    int nx, ny, nz;
+    int sh[6];
+    double hk2;          // h^2 kappa^2
+    double* partials;    // 3 per block
+};
+
+__global__ __launch_bounds__(kPbThreads) void k_pb_residual(PbParams P)
+{
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int rows = ny * nz;
+    const size_t plane = (size_t)nx * ny;
+    double r2 = 0.0, b2 = 0.0, m = 0.0;
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int j = row % ny, k = row / ny;
+        const size_t base = (size_t)row * nx;
+        for (int i = threadIdx.x; i < nx; i += kPbThreads) {
+            const size_t c = base + i;
+            const double p = P.psi[c];
+            // neighbours in the order x-, x+, y-, y+, z-, z+; outside the domain the
+            // face's condition moves to the centre (folded boundary conditions)
+            double nb = 0.0;
+            int d = 6;
+            if (i > 0) nb += P.psi[c - 1]; else d += P.sh[0];
+            if (i < nx - 1) nb += P.psi[c + 1]; else d += P.sh[1];
+            if (j > 0) nb += P.psi[c - nx]; else d += P.sh[2];
+            if (j < ny - 1) nb += P.psi[c + nx]; else d += P.sh[3];
+            if (k > 0) nb += P.psi[c - plane]; else d += P.sh[4];
+            if (k < nz - 1) nb += P.psi[c + plane]; else d += P.sh[5];
+            const double b = P.bt[c];
+            const double r = b - ((double)d * p - nb) - P.hk2 * sinh(p);
+            P.r[c] = r;
+            r2 += r * r;
+            b2 += b * b;
+            m = fmax(m, fabs(p));
+        }
+    }
+    __shared__ double red[3][kPbThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    r2 = wave_sum(r2);
+    b2 = wave_sum(b2);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if (lane == 0) { red[0][w] = r2; red[1][w] = b2; red[2][w] = m; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0, mm = 0.0;
+        for (int i = 0; i < kPbThreads / 64; ++i) { a += red[0][i]; b += red[1][i]; mm = fmax(mm, red[2][i]); }
+        P.partials[3 * blockIdx.x] = a;
+        P.partials[3 * blockIdx.x + 1] = b;
+        P.partials[3 * blockIdx.x + 2] = mm;
+    }
+}
+
+// One block: the partials in block order; relative nonlinear residual of
+// step `cycle` into the control block (cycle 0 also records ||b-tilde||).
+// done: converged (rel < rtol), b-tilde = 0 (psi = 0 solves it), or not finite.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pb_finish(const double* partials, int nblk, Ctl* ctl, int cycle)
+{
+    __shared__ double red[3][NT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double a = 0.0, b = 0.0, m = 0.0;
+    for (int i = tid; i < nblk; i += NT) {
+        a += partials[3 * i];
+        b += partials[3 * i + 1];
+        m = fmax(m, partials[3 * i + 2]);
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if (lane == 0) { red[0][w] = a; red[1][w] = b; red[2][w] = m; }
+    __syncthreads();
+    if (tid != 0) return;
+    double r2 = 0.0, b2 = 0.0, mm = 0.0;
+    for (int i = 0; i < NT / 64; ++i) { r2 += red[0][i]; b2 += red[1][i]; mm = fmax(mm, red[2][i]); }
+    const double rn = sqrt(r2), bn = sqrt(b2);
+    const bool finite = isfinite(rn) && isfinite(bn) && isfinite(mm);
+    const double rel = !finite ? (double)NAN : (bn > 0.0 ? rn / bn : 0.0);
+    ctl->rnorm = rn;
+    ctl->rel = rel;
+    ctl->pb_max = mm;
+    if (cycle < kMaxHist) ctl->hist[cycle] = rel;
+    ctl->cycles = cycle;
+    if (cycle == 0) {
+        ctl->bnorm = bn;
+        ctl->bzero = finite && bn == 0.0;
+    }
+    if (!finite) ctl->status = -5;
+    ctl->done = !finite || ctl->bzero || !(rel >= ctl->rtol);
+}
+
+__global__ void k_axpy(double* y, const double* x, size_t n)
+{
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
+        y[c] += x[c];
 }
 
 // ---------------------------------------------------------------------------
