@@ -234,6 +234,54 @@ def variable_eps_solve(w: W.Workload, sph, sph_dev, dev, steps: int, warmup: int
             "permittivity": "2.5 inside the 200 spheres, 78.5 elsewhere (jump 31x)"}
 
 
+def poisson_boltzmann(dev, steps: int, warmup: int, kappa: float = 0.25, charge_scale: float = 100.0):
+    """The 256^3 workload's spheres as charged particles in an electrolyte
+    (Poisson-Boltzmann, the equation the paper's outlook names): Debye length
+    1/kappa = 4 cells, charges scaled so that the double layers reach a few
+    thermal potentials.  The linearised (Debye-Hueckel) solve to 1e-10 in FP64
+    and with FP32 refinement, and the nonlinear solve (shifted chord
+    iteration, two V-cycles per step) to 1e-10, each from zero, timed."""
+    w = W.C2
+    sph = W.workload_spheres(w)
+    c, r, q = (torch.tensor(a, device=dev) for a in (sph.centers, sph.radii, sph.charges))
+    res = {"workload": w.name, "cells": list(w.shape), "spheres": w.n_spheres, "kappa": kappa,
+           "debye_length_cells": 1.0 / kappa, "charge_scale": charge_scale,
+           "equation": "-Lap(psi) + kappa^2 sinh(psi) = f (linear: kappa^2 psi)"}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed_runs(fn):
+        for _ in range(warmup):
+            out = fn()
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(steps):
+            out = fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / steps, out
+
+    for prec, key in ((pkg.FP64, "linear_fp64"), (pkg.FP32_IR, "linear_fp32_ir"), (pkg.FP64, "nonlinear_fp64")):
+        opt = pkg.Options(levels=w.levels, nu1=w.nu1, nu2=w.nu2, omega=w.omega, precision=prec, kappa2=kappa ** 2)
+        s = pkg.Solver(w.shape, w.h, list(zip(w.kinds, w.values)), opt, device=dev)
+        f = s.zeros()
+        s.deposit(c, r, q * charge_scale, w.eps, out=f)
+        psi = s.zeros()
+        if key.startswith("linear"):
+            ms, (_, st) = timed_runs(lambda: s.solve(f, psi, rtol=w.rtol, zero_guess=True))
+            res[key] = {"ms_per_solve": ms, "unknowns_per_s": w.cells / (ms * 1e-3), "cycles": st.cycles,
+                        "final_rel_res": st.rel_res}
+        else:
+            def nl():
+                psi.zero_()
+                return s.solve_pb(f, psi, rtol=w.rtol, max_outer=300, inner=2)
+            ms, (_, st) = timed_runs(nl)
+            res[key] = {"ms_per_solve": ms, "unknowns_per_s": w.cells / (ms * 1e-3), "outer_steps": st.cycles,
+                        "v_cycles": st.inner_cycles, "final_rel_res": st.rel_res,
+                        "max_abs_psi": psi.abs().max().item()}
+        del s
+    return res
+
+
 def forward_adjoint(dev, steps: int, warmup: int, weight_seed: int = 2005):
     """The microchannel workload (1024 x 256 x 256, 10,000 spheres, 7 levels)
     as a differentiable step: deposition, the forward solve from zero, then
@@ -408,11 +456,12 @@ def main():
     ap.add_argument("--no-scene", action="store_true", help="skip the time-step scene")
     ap.add_argument("--no-c2", action="store_true", help="skip the 256^3 workload section")
     ap.add_argument("--no-vc", action="store_true", help="skip the variable-permittivity solve")
+    ap.add_argument("--no-pb", action="store_true", help="skip the Poisson-Boltzmann solves")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the microchannel forward + adjoint step (FP64 and FP32 refinement)")
     ap.add_argument("--all-configs", action="store_true",
                     help="time every workload on the GPU next to the CPU oracle and print that JSON instead")
-    ap.add_argument("--only", choices=("scene", "vc", "adjoint"), default=None,
+    ap.add_argument("--only", choices=("scene", "vc", "adjoint", "pb"), default=None,
                     help="run one secondary section alone and print its JSON object (for profiling runs)")
     ap.add_argument("--scene-steps", type=int, default=240)
     ap.add_argument("--calib-copy", action="store_true",
@@ -435,6 +484,9 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps({"forward_adjoint": forward_adjoint(dev, args.steps, args.warmup)}), flush=True)
+        return
+    if args.only == "pb":
+        print(json.dumps({"poisson_boltzmann": poisson_boltzmann(dev, args.steps, args.warmup)}), flush=True)
         return
     if args.only == "vc":
         print(json.dumps({"variable_eps": variable_eps_solve(w, sph, sph_dev, dev, args.steps, args.warmup)}),
@@ -575,6 +627,13 @@ def main():
         sph_vd = tuple(torch.tensor(a, device=dev) for a in (sph_v.centers, sph_v.radii, sph_v.charges))
         out["variable_eps"] = vc = variable_eps_solve(wv, sph_v, sph_vd, dev, max(1, args.steps // 2), 1)
         log(f"variable eps: {vc['ms_per_step']:.3f} ms/step, {vc['cycles']} cycles, rel {vc['final_rel_res']:.2e}")
+
+    if not args.no_pb:
+        out["poisson_boltzmann"] = pb = poisson_boltzmann(dev, max(1, args.steps // 4), 1)
+        log(f"poisson-boltzmann 256^3: linear {pb['linear_fp64']['ms_per_solve']:.2f} ms "
+            f"({pb['linear_fp64']['cycles']} cycles), fp32-ir {pb['linear_fp32_ir']['ms_per_solve']:.2f} ms, "
+            f"nonlinear {pb['nonlinear_fp64']['ms_per_solve']:.2f} ms ({pb['nonlinear_fp64']['outer_steps']} steps, "
+            f"max|psi| {pb['nonlinear_fp64']['max_abs_psi']:.2f})")
 
     if not args.no_adjoint:
         out["forward_adjoint"] = fa = forward_adjoint(dev, max(1, args.steps // 4), 1)
