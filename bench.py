@@ -34,9 +34,9 @@ import paper_1410_6609_amd as pkg  # noqa: E402
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
-KERNEL_NAMES = {   # finest-level passes of a V(2,2) cycle, two sweeps fused per pass
-    "pre": "void k_pass<double, 4, 0, 1, 2, 8>",
-    "post": "void k_pass<double, 4, 2, 2, 2, 8>",
+KERNEL_NAMES = {   # finest-level passes of a V(2,2) cycle, two sweeps fused per pass (long z-marches)
+    "pre": "void k_pass<double, 4, 0, 1, 2, 8, true>",
+    "post": "void k_pass<double, 4, 2, 2, 2, 8, true>",
 }
 
 
