@@ -204,12 +204,16 @@ constexpr size_t kBottomMaxLds = 160 * 1024;
 constexpr int kPadMinPlanes = 64;   // z-chunks from which FP64 passes march whole unrolled blocks
 constexpr int kFoldMaxBlocks = 4096;   // grid of the fold (grid-stride over x-rows)
 
+#ifndef CCMG_ROWS_SINGLE
+#define CCMG_ROWS_SINGLE 2
+#endif
 template <typename T, int SPHI, int LOAD, int RES>
 bool launch_one(const PassParams<T>& P0, hipStream_t st)
 {
     constexpr int WYT = kWYof<T>;
-    using Sh = PassShape<T, SPHI, RES, kM, WYT, LOAD>;
-    auto kern = k_pass<T, SPHI, LOAD, RES, kM, WYT>;
+    constexpr int MT = (sizeof(T) == 8 && SPHI == 0) ? CCMG_ROWS_SINGLE : kM;
+    using Sh = PassShape<T, SPHI, RES, MT, WYT, LOAD>;
+    auto kern = k_pass<T, SPHI, LOAD, RES, MT, WYT>;
     static int per_cu = 0;
     if (per_cu == 0) {
         int nb = 0;
@@ -233,7 +237,7 @@ bool launch_one(const PassParams<T>& P0, hipStream_t st)
     // long FP64 marches run whole unrolled blocks of steps (k_pass PAD)
     constexpr bool kPadKernel = sizeof(T) == 8 && SPHI > 0;
     if (kPadKernel && g.zc >= kPadMinPlanes)
-        hipLaunchKernelGGL((k_pass<T, SPHI, LOAD, RES, kM, WYT, kPadKernel>), dim3(g.blocks()), dim3(64 * WYT), 0, st, P);
+        hipLaunchKernelGGL((k_pass<T, SPHI, LOAD, RES, MT, WYT, kPadKernel>), dim3(g.blocks()), dim3(64 * WYT), 0, st, P);
     else
         hipLaunchKernelGGL(kern, dim3(g.blocks()), dim3(64 * WYT), 0, st, P);
     if constexpr (kNormRes)
@@ -953,19 +957,32 @@ int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_
     } else {
         inner = s->opt.ir_inner_cycles;
         const LevelPtrs<float> H = fp32_ptrs(s);
-        // first scaled FP32 residual of the initial guess (re-finalises cycle 0)
-        rc = enqueue_norm(s, no_load ? nullptr : phi, FIN_CYCLE, RES_NORM_R32, nullptr, s->lv[0].b32, 0);
-        if (rc) return rc;
+        // first scaled FP32 residual of the initial guess (re-finalises cycle 0);
+        // from the zero guess it is b-tilde, whose norm is finalised above
+        if (no_load) {
+            hipLaunchKernelGGL(k_first_r32, dim3(grid1d(B0.n / 2 + 1)), dim3(256), 0, s->stream, (const double*)B0.b,
+                               s->lv[0].b32, B0.n, s->ctl);
+            LAUNCHCHK(s);
+        } else {
+            rc = enqueue_norm(s, phi, FIN_CYCLE, RES_NORM_R32, nullptr, s->lv[0].b32, 0);
+            if (rc) return rc;
+        }
         double* tmp = s->lv[0].tmp;
-        // step k reads the iterate from phi (k odd) or tmp (k even) and writes the other one
+        // Step k reads the iterate written by step k - 1 and writes the other
+        // buffer.  From the zero guess the first step reads nothing and may
+        // write either one: it is chosen so that the step count of the last
+        // solve ends in phi, which spares the final copy when the count repeats.
+        const int k_pred = s->last_cycles > 0 ? s->last_cycles : 3;
+        const bool flip = no_load && (k_pred & 1);
+        auto out_buf = [&](int k) { return (((k & 1) == 0) != flip) ? phi : tmp; };
         auto step = [&](int k) -> int {
             for (int m = 0; m < inner; ++m) {
                 int r = enqueue_vcycle<float>(s, H, m == 0, 0);
                 if (r) return r;
             }
             PassParams<double> P = base_params<double>(s, 0);
-            P.phi_in = (k & 1) ? (no_load && k == 1 ? nullptr : phi) : tmp;
-            P.phi_out = (k & 1) ? tmp : phi;
+            P.phi_in = k == 1 ? (no_load ? nullptr : phi) : out_buf(k - 1);
+            P.phi_out = out_buf(k);
             P.b = s->lv[0].b;
             P.corr = s->lv[0].phi32;
             P.r32_out = s->lv[0].b32;
@@ -977,7 +994,7 @@ int solve_folded(ccmg_solver* s, double* phi, double rtol, int max_cycles, ccmg_
         };
         rc = run_loop(s, max_cycles, step, h);
         if (rc) return rc;
-        if (h.cycles & 1) {
+        if (h.cycles >= 1 && out_buf(h.cycles) == tmp) {
             // the last finished step left the iterate in tmp
             hipLaunchKernelGGL((k_copy<double>), dim3(grid1d(B0.n)), dim3(256), 0, s->stream, (const double*)tmp, phi,
                                B0.n, (const Ctl*)nullptr);

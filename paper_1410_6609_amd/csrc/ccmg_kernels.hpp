@@ -1403,6 +1403,29 @@ __global__ void k_copy(const T* src, T* dst, size_t n, const Ctl* ctl)
         dst[c] = src[c];
 }
 
+// First scaled FP32 residual of a refinement from the zero guess: the
+// residual is b-tilde itself, whose norm and scale the initial norm already
+// finalised (cycle 0), so the stencil pass reduces to this stream:
+// dst = (float)(src / sig_next), and sig_cur takes sig_next, as the
+// finalisation of cycle 0 does.
+__global__ __launch_bounds__(256) void k_first_r32(const double* __restrict__ src, float* __restrict__ dst, size_t n,
+                                                   Ctl* ctl)
+{
+    if (ctl->done) return;
+    const double inv = 1.0 / ctl->sig_next;
+    const size_t n2 = n / 2;
+    const double2* s2 = reinterpret_cast<const double2*>(src);
+    float2* d2 = reinterpret_cast<float2*>(dst);
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n2; c += (size_t)gridDim.x * blockDim.x) {
+        const double2 v = s2[c];
+        d2[c] = make_float2((float)(v.x * inv), (float)(v.y * inv));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (n & 1) dst[n - 1] = (float)(src[n - 1] * inv);
+        ctl->sig_cur = ctl->sig_next;
+    }
+}
+
 __global__ void k_scale(const double* src, double* dst, size_t n, double a)
 {
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
