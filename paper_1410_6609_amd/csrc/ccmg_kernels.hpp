@@ -453,13 +453,20 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     // byte offsets in a plane: loads (in the domain), stores (owned by this
     // tile), parents of the prolongation and coarse cells of the restriction;
     // kOob where the lane must not access
-    unsigned offL[M], offS[M], offL4[M];
+    // b-tilde is read by stage s >= 1 only where that stage is exact, rows
+    // [s, EY - 1 - s] of the tile (x pairs [s, EX - 1 - s]): never on the outermost
+    // loaded rows, and in a single-stage pass not in the outermost x pairs either
+    // (those values feed only cells that are inexact anyway), so they are not loaded
+    unsigned offL[M], offS[M], offL4[M], offB[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         const unsigned e = (unsigned)((ybase + r) * nx + xl);
         offL[r] = vrow[r] ? e * (unsigned)sizeof(T) : kOob;
         offS[r] = (vrow[r] && yin[r] && xin) ? e * (unsigned)sizeof(T) : kOob;
         offL4[r] = vrow[r] ? e * 4u : kOob;   // the FP32 correction of LOAD_CORR
+        const int ry = strip * M + r;
+        const bool bskip = ry == 0 || ry == Sh::EY - 1 || (S == 1 && (xp == 0 || xp == 31));
+        offB[r] = bskip ? kOob : offL[r];
     }
     auto coarse_off = [&](int r, bool ok) -> unsigned {
         return ok ? (unsigned)((((ybase + r) >> 1) * cnx + (xl >> 1)) * (int)sizeof(T)) : kOob;
@@ -521,7 +528,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
         const auto rc = plane_rsrc(P.corr, plane * sizeof(float), t, zin && LOAD == LOAD_CORR);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
-            bload2(rb, offL[r], nbb[k][r][0], nbb[k][r][1]);
+            bload2(rb, offB[r], nbb[k][r][0], nbb[k][r][1]);
             if constexpr (LOAD != LOAD_ZERO) bload2(rp, offL[r], nph[k][r][0], nph[k][r][1]);
             else { nph[k][r][0] = T(0); nph[k][r][1] = T(0); }
             if constexpr (LOAD == LOAD_CORR) bload2(rc, offL4[r], ncr[k][r][0], ncr[k][r][1]);

@@ -43,11 +43,17 @@ def reference(shape, levels, n, precision, f):
 
 def test_static_scratch_solve_matches_workspace_solve():
     results = []
+    # one right-hand side per case, reused by the repeated case: cells covered
+    # by three spheres take their charges by atomics in no fixed order, so two
+    # depositions can differ in the last bit
+    rhs_of = {}
     for shape, levels, n, precision in CASES + CASES[:1]:
         print(f"static-scratch solve {shape} levels={levels} precision={precision}", flush=True)
         w, s = problem(shape, levels, n, precision, False)
         assert s.workspace is None
-        f = rhs(w)
+        if shape not in rhs_of:
+            rhs_of[shape] = rhs(w)
+        f = rhs_of[shape]
         phi_ref, st_ref = reference(shape, levels, n, precision, f)
         nx, ny, nz = shape
         phi = torch.full((nz, ny, nx), float("nan"), dtype=torch.float64, device=DEV)
