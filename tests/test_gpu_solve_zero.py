@@ -41,6 +41,26 @@ def test_solve_zero_matches_zeroed_guess(case, precision):
     assert torch.equal(p0, p2) and st2.cycles == st0.cycles
 
 
+def test_fp32_ir_zero_guess_any_step_count():
+    """From the zero guess the first refinement step writes whichever buffer
+    lets the previous solve's step count end in phi; here the count changes
+    from solve to solve (rtol = 0, fixed step counts of both parities), so
+    the guess is right or wrong in turn and the result must still be the
+    iterate of ccmg_solve on a zeroed phi, bit for bit."""
+    shape, levels, kinds, values = CASES[1]
+    log_case("solve_zero ir step counts", shape)
+    s = solver_for(shape, levels, kinds, values, precision=pkg.FP32_IR)
+    r = solver_for(shape, levels, kinds, values, precision=pkg.FP32_IR)
+    f = to_dev(rhs(shape, 14))
+    for k in (3, 2, 4, 1, 3, 3, 2, 2):
+        p_ref = r.zeros()
+        _, st_ref = r.solve(f, p_ref, rtol=0.0, max_cycles=k, check=False)
+        p = nan_field(shape)
+        _, st = s.solve(f, p, rtol=0.0, max_cycles=k, zero_guess=True, check=False)
+        assert st.cycles == st_ref.cycles == k
+        assert torch.equal(p, p_ref), (k, float((p - p_ref).abs().max()))
+
+
 def test_solve_zero_variable_permittivity():
     shape, levels, kinds, values = CASES[1]
     log_case("solve_zero vc", shape)
