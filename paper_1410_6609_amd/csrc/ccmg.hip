@@ -204,16 +204,12 @@ constexpr size_t kBottomMaxLds = 160 * 1024;
 constexpr int kPadMinPlanes = 64;   // z-chunks from which FP64 passes march whole unrolled blocks
 constexpr int kFoldMaxBlocks = 4096;   // grid of the fold (grid-stride over x-rows)
 
-#ifndef CCMG_ROWS_SINGLE
-#define CCMG_ROWS_SINGLE 2
-#endif
 template <typename T, int SPHI, int LOAD, int RES>
 bool launch_one(const PassParams<T>& P0, hipStream_t st)
 {
     constexpr int WYT = kWYof<T>;
-    constexpr int MT = (sizeof(T) == 8 && SPHI == 0) ? CCMG_ROWS_SINGLE : kM;
-    using Sh = PassShape<T, SPHI, RES, MT, WYT, LOAD>;
-    auto kern = k_pass<T, SPHI, LOAD, RES, MT, WYT>;
+    using Sh = PassShape<T, SPHI, RES, kM, WYT, LOAD>;
+    auto kern = k_pass<T, SPHI, LOAD, RES, kM, WYT>;
     static int per_cu = 0;
     if (per_cu == 0) {
         int nb = 0;
@@ -237,7 +233,7 @@ bool launch_one(const PassParams<T>& P0, hipStream_t st)
     // long FP64 marches run whole unrolled blocks of steps (k_pass PAD)
     constexpr bool kPadKernel = sizeof(T) == 8 && SPHI > 0;
     if (kPadKernel && g.zc >= kPadMinPlanes)
-        hipLaunchKernelGGL((k_pass<T, SPHI, LOAD, RES, MT, WYT, kPadKernel>), dim3(g.blocks()), dim3(64 * WYT), 0, st, P);
+        hipLaunchKernelGGL((k_pass<T, SPHI, LOAD, RES, kM, WYT, kPadKernel>), dim3(g.blocks()), dim3(64 * WYT), 0, st, P);
     else
         hipLaunchKernelGGL(kern, dim3(g.blocks()), dim3(64 * WYT), 0, st, P);
     if constexpr (kNormRes)
