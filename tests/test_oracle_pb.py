@@ -225,3 +225,23 @@ def test_kappa_zero_is_poisson(orc):
     # the nonlinear iteration with k2 = 0 is defect correction by V-cycles
     p2, h2, st = orc.pb_nl_solve(b, h, kinds, 4, 0.0, inner=1, rtol=1e-12)
     assert st == 0 and np.abs(p2 - p0).max() <= 1e-11 * np.abs(p0).max()
+
+
+@pytest.mark.parametrize("kinds", BC_SETS[:3])
+def test_nonlinear_residual(orc, kinds):
+    """The nonlinear residual b - A psi - kappa^2 sinh(psi): zero (to rounding)
+    at a manufactured solution, and at a random potential equal to the
+    residual formed with the assembled linear operator (its columns from the
+    pinned operator) and the library sinh."""
+    shape, h, k2 = (6, 4, 8), 1.0 / 8, 30.0
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(*[(np.arange(n) + 0.5) * h for n in (nz, ny, nx)], indexing="ij")
+    psi_star = 2.0 * np.sin(2.1 * x + 0.3) * np.cos(1.3 * y) * np.exp(-0.7 * z)
+    b = orc.apply(psi_star, h, kinds) + k2 * np.sinh(psi_star)
+    r = orc.pb_nl_residual(psi_star, b, h, kinds, k2)
+    assert np.abs(r).max() <= 1e-12 * np.abs(b).max()
+    A = dense_pb(orc, shape, h, kinds, 0.0)
+    psi = 1.5 * np.random.default_rng(41).standard_normal((nz, ny, nx))
+    ref = b.ravel() - A @ psi.ravel() - k2 * np.sinh(psi.ravel())
+    got = orc.pb_nl_residual(psi, b, h, kinds, k2).ravel()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()

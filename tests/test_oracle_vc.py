@@ -228,3 +228,30 @@ def test_periodic_gradient_of_a_sine(orc):
     assert np.allclose(g[0][inner], np.broadcast_to(want, (nz, ny, nx))[inner], rtol=0, atol=1e-13)
     # the boundary layers of y/z use D3Q7 in x, also exact: (phi(x+h) - phi(x-h)) / 2h
     assert np.allclose(g[0][0], np.broadcast_to(want, (ny, nx)), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("kinds", KINDS + PERIODIC_KINDS)
+@pytest.mark.parametrize("level", [0, 1])
+def test_vc_rbgs_equals_dense_gauss_seidel(orc, kinds, level):
+    """One variable-permittivity red-black sweep is one Gauss-Seidel sweep over
+    the unknowns ordered red first, then black (Sec. 5.3), on the operator whose
+    columns vc_apply gives (itself pinned above); two sweeps are two of them."""
+    shape, h = (4, 6, 4), 0.4
+    nx, ny, nz = shape
+    fine = (2 * nx, 2 * ny, 2 * nz) if level else shape
+    k = orc.vc_faces(random_eps(fine, 31), kinds)
+    if level:
+        k = orc.vc_coarsen(k)
+    A = vc_dense(orc, shape, h, kinds, k, level)
+    rng = np.random.default_rng(32)
+    n = A.shape[0]
+    b = rng.standard_normal(n)
+    phi0 = rng.standard_normal(n)
+    col = ((np.arange(n) % nx) + (np.arange(n) // nx) % ny + np.arange(n) // (nx * ny)) % 2
+    order = list(np.flatnonzero(col == 0)) + list(np.flatnonzero(col == 1))
+    x = phi0.copy()
+    for sweep in range(2):
+        for c in order:
+            x[c] = (b[c] - (A[c] @ x - A[c, c] * x[c])) / A[c, c]
+        got = orc.vc_rbgs_sweep(phi0.reshape(nz, ny, nx), b.reshape(nz, ny, nx), h, kinds, k, level, sweeps=sweep + 1)
+        assert np.abs(got.ravel() - x).max() <= 1e-13 * max(1.0, np.abs(x).max()), sweep
