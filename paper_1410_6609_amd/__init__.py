@@ -21,7 +21,7 @@ import torch
 
 __all__ = [
     "DIRICHLET", "NEUMANN", "PERIODIC", "FP64", "FP32_IR", "SPREAD", "VOLUME", "CcmgError", "Options", "Stats", "Solver",
-    "PoissonFn", "RhsSolveFn", "lib", "LIB_PATH", "exported_symbols",
+    "PoissonFn", "RhsSolveFn", "lib", "load_library", "LIB_PATH", "exported_symbols",
 ]
 
 DIRICHLET, NEUMANN, PERIODIC = 0, 1, 2
@@ -143,18 +143,25 @@ def exported_symbols() -> Sequence[str]:
     return tuple(_SIGS)
 
 
+def load_library(path: str) -> ctypes.CDLL:
+    """Load a build of the library at `path` with the C signatures set (for
+    Solver(library=...): another build of the same sources, e.g. other tile
+    macros).  Raises if the file is missing."""
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python paper_1410_6609_amd/build.py`")
+    L = ctypes.CDLL(path)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
 def lib() -> ctypes.CDLL:
     """Load libccmg.so (built by paper_1410_6609_amd/build.py); raise if it is missing."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1410_6609_amd/build.py`")
-        L = ctypes.CDLL(LIB_PATH)
-        for name, (args, res) in _SIGS.items():
-            fn = getattr(L, name)
-            fn.argtypes = args
-            fn.restype = res
-        _lib = L
+        _lib = load_library(LIB_PATH)
     return _lib
 
 
@@ -174,7 +181,8 @@ class Solver:
     """
 
     def __init__(self, shape: Tuple[int, int, int], h: float, faces: Sequence[Tuple[int, float]],
-                 options: Optional[Options] = None, device="cuda", workspace: bool = True):
+                 options: Optional[Options] = None, device="cuda", workspace: bool = True,
+                 library: Optional[ctypes.CDLL] = None):
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("the solver runs on a GPU device only")
@@ -184,7 +192,8 @@ class Solver:
         if len(self.faces) != 6:
             raise ValueError("six faces required")
         self.options = options or Options()
-        L = lib()
+        L = lib() if library is None else library   # every call of this solver goes to L
+        self._L = L
         arr = (_Face * 6)(*[_Face(k, v) for k, v in self.faces])
         opt = self.options._c()
         handle = ctypes.c_void_p()
@@ -206,18 +215,18 @@ class Solver:
 
     # -- plumbing -------------------------------------------------------------
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and _lib is not None:
-            _lib.ccmg_destroy(h)
+        h, L = getattr(self, "_h", None), getattr(self, "_L", None)
+        if h is not None and L is not None:
+            L.ccmg_destroy(h)
             self._h = None
 
     def _check(self, rc: int, allow=()):
         if rc != OK and rc not in allow:
-            raise CcmgError(rc, lib().ccmg_last_error(self._h).decode())
+            raise CcmgError(rc, self._L.ccmg_last_error(self._h).decode())
         return rc
 
     def _bind_stream(self):
-        lib().ccmg_set_stream(self._h, _stream_handle(self.device))
+        self._L.ccmg_set_stream(self._h, _stream_handle(self.device))
 
     def _field(self, t: torch.Tensor, name: str) -> torch.Tensor:
         nx, ny, nz = self.shape
@@ -238,11 +247,11 @@ class Solver:
 
     @property
     def levels(self) -> int:
-        return lib().ccmg_num_levels(self._h)
+        return self._L.ccmg_num_levels(self._h)
 
     def level_dims(self, l: int) -> Tuple[int, int, int]:
         d = (ctypes.c_int * 3)()
-        self._check(lib().ccmg_level_dims(self._h, l, d))
+        self._check(self._L.ccmg_level_dims(self._h, l, d))
         return tuple(d)
 
     def zeros(self) -> torch.Tensor:
@@ -264,11 +273,11 @@ class Solver:
         self._bind_stream()
         if subsample == 1 and mode == SPREAD:
             cnt = torch.zeros(n, dtype=torch.int32, device=self.device) if counts else None
-            self._check(lib().ccmg_deposit_charges(self._h, n, _ptr(centers), _ptr(radii), _ptr(q), float(eps),
+            self._check(self._L.ccmg_deposit_charges(self._h, n, _ptr(centers), _ptr(radii), _ptr(q), float(eps),
                                                    _ptr(f), _ptr(cnt)))
         else:
             cnt = torch.zeros(n, dtype=torch.float64, device=self.device) if counts else None
-            self._check(lib().ccmg_deposit_charges_sub(self._h, n, _ptr(centers), _ptr(radii), _ptr(q), float(eps),
+            self._check(self._L.ccmg_deposit_charges_sub(self._h, n, _ptr(centers), _ptr(radii), _ptr(q), float(eps),
                                                        int(subsample), int(mode), _ptr(f), _ptr(cnt)))
         return (f, cnt) if counts else f
 
@@ -279,7 +288,7 @@ class Solver:
         c, r = self._spheres(centers, radii)
         dq = torch.zeros(r.shape[0], dtype=torch.float64, device=self.device)
         self._bind_stream()
-        self._check(lib().ccmg_charge_gradient(self._h, r.shape[0], _ptr(c), _ptr(r), float(eps), int(subsample),
+        self._check(self._L.ccmg_charge_gradient(self._h, r.shape[0], _ptr(c), _ptr(r), float(eps), int(subsample),
                                                int(mode), _ptr(lam), _ptr(dq)))
         return dq
 
@@ -292,7 +301,7 @@ class Solver:
                 or not g.is_contiguous()):
             raise ValueError("out must be a contiguous float64 tensor of shape (3, nz, ny, nx)")
         self._bind_stream()
-        self._check(lib().ccmg_gradient(self._h, _ptr(phi), _ptr(g)))
+        self._check(self._L.ccmg_gradient(self._h, _ptr(phi), _ptr(g)))
         return g
 
     def coulomb_force(self, phi: torch.Tensor, centers, radii, q, subsample: int = 1, mode: int = SPREAD,
@@ -308,7 +317,7 @@ class Solver:
         if tuple(F.shape) != (n, 3) or F.dtype != torch.float64 or F.device != self.device or not F.is_contiguous():
             raise ValueError(f"out must be a contiguous float64 tensor of shape ({n}, 3) on {self.device}")
         self._bind_stream()
-        self._check(lib().ccmg_coulomb_force(self._h, _ptr(phi), n, _ptr(c), _ptr(r), _ptr(q), int(subsample),
+        self._check(self._L.ccmg_coulomb_force(self._h, _ptr(phi), n, _ptr(c), _ptr(r), _ptr(q), int(subsample),
                                              int(mode), _ptr(F)))
         return F
 
@@ -325,7 +334,7 @@ class Solver:
         mu = self.zeros()
         direct = torch.zeros(n, dtype=torch.float64, device=self.device)
         self._bind_stream()
-        self._check(lib().ccmg_coulomb_adjoint(self._h, _ptr(phi), n, _ptr(c), _ptr(r), _ptr(q), int(subsample),
+        self._check(self._L.ccmg_coulomb_adjoint(self._h, _ptr(phi), n, _ptr(c), _ptr(r), _ptr(q), int(subsample),
                                                int(mode), _ptr(gF), _ptr(mu), _ptr(direct)))
         return mu, direct
 
@@ -346,7 +355,7 @@ class Solver:
         dq = torch.zeros(n, dtype=torch.float64, device=self.device)
         st = _Stats()
         self._bind_stream()
-        self._check(lib().ccmg_force_charge_gradient(
+        self._check(self._L.ccmg_force_charge_gradient(
             self._h, _ptr(phi), n, _ptr(c), _ptr(r), _ptr(q), float(eps), int(force_subsample), int(force_mode),
             int(deposit_subsample), int(deposit_mode), _ptr(gF), _ptr(mu), _ptr(lam), _ptr(dq), float(rtol),
             int(max_cycles), ctypes.byref(st)))
@@ -359,7 +368,7 @@ class Solver:
         if eps is not None:
             v = self._field(eps.to(self.device, torch.float64).contiguous(), "eps")
         self._bind_stream()
-        self._check(lib().ccmg_set_permittivity(self._h, _ptr(v)))
+        self._check(self._L.ccmg_set_permittivity(self._h, _ptr(v)))
         self._eps_keep = v   # read by the enqueued kernels
 
     def set_face_values(self, face: int, values: Optional[torch.Tensor]) -> None:
@@ -373,7 +382,7 @@ class Solver:
             if tuple(v.shape) != shape[face]:
                 raise ValueError(f"face {face} values must have shape {shape[face]}")
         self._bind_stream()
-        self._check(lib().ccmg_set_face_values(self._h, int(face), _ptr(v)))
+        self._check(self._L.ccmg_set_face_values(self._h, int(face), _ptr(v)))
         self._face_keep = getattr(self, "_face_keep", {})
         self._face_keep[face] = v   # the copy is stream-ordered: keep the source until it ran
 
@@ -391,7 +400,7 @@ class Solver:
             phi = self._field(phi, "phi")
         st = _Stats()
         self._bind_stream()
-        fn = lib().ccmg_solve_zero if zero_guess else lib().ccmg_solve
+        fn = self._L.ccmg_solve_zero if zero_guess else self._L.ccmg_solve
         rc = fn(self._h, _ptr(phi), _ptr(f), float(rtol), int(max_cycles), ctypes.byref(st))
         if check:
             self._check(rc)
@@ -407,7 +416,7 @@ class Solver:
         phi = self._field(phi, "phi")
         st = _Stats()
         self._bind_stream()
-        rc = lib().ccmg_solve_zero_static(self._h, _ptr(phi), _ptr(f), float(rtol), int(max_cycles),
+        rc = self._L.ccmg_solve_zero_static(self._h, _ptr(phi), _ptr(f), float(rtol), int(max_cycles),
                                           ctypes.byref(st))
         if check:
             self._check(rc)
@@ -422,7 +431,7 @@ class Solver:
         psi = self.zeros() if psi is None else self._field(psi, "psi")
         st = _Stats()
         self._bind_stream()
-        rc = lib().ccmg_solve_pb(self._h, _ptr(psi), _ptr(f), float(rtol), int(max_outer), int(inner),
+        rc = self._L.ccmg_solve_pb(self._h, _ptr(psi), _ptr(f), float(rtol), int(max_outer), int(inner),
                                  ctypes.byref(st))
         if check:
             self._check(rc)
@@ -433,7 +442,7 @@ class Solver:
         phi = self._field(phi, "phi")
         out = ctypes.c_double(0.0)
         self._bind_stream()
-        self._check(lib().ccmg_vcycle(self._h, _ptr(phi), _ptr(f), ctypes.byref(out) if norm else None))
+        self._check(self._L.ccmg_vcycle(self._h, _ptr(phi), _ptr(f), ctypes.byref(out) if norm else None))
         return out.value if norm else None
 
     def vcycles(self, phi: torch.Tensor, f: torch.Tensor, ncycles: int,
@@ -447,7 +456,7 @@ class Solver:
                                     or rel_out.numel() != 1):
             raise ValueError("rel_out must be one float64 element on the solver's device")
         self._bind_stream()
-        self._check(lib().ccmg_vcycles(self._h, _ptr(phi), _ptr(f), int(ncycles), _ptr(rel_out)))
+        self._check(self._L.ccmg_vcycles(self._h, _ptr(phi), _ptr(f), int(ncycles), _ptr(rel_out)))
         return phi
 
     def adjoint(self, g: torch.Tensor, centers=None, radii=None, eps: float = 1.0, rtol: float = 1e-10,
@@ -469,13 +478,13 @@ class Solver:
         st = _Stats()
         self._bind_stream()
         nn = n if naive else 0
-        rc = lib().ccmg_adjoint_solve(self._h, _ptr(g), _ptr(lam), nn, _ptr(c), _ptr(r), float(eps),
+        rc = self._L.ccmg_adjoint_solve(self._h, _ptr(g), _ptr(lam), nn, _ptr(c), _ptr(r), float(eps),
                                       _ptr(dq) if naive else None, _ptr(drho), float(rtol), int(max_cycles),
                                       ctypes.byref(st))
         if check:
             self._check(rc)
         if n > 0 and not naive and rc in (OK, E_NOCONV):
-            self._check(lib().ccmg_charge_gradient(self._h, n, _ptr(c), _ptr(r), float(eps), int(subsample),
+            self._check(self._L.ccmg_charge_gradient(self._h, n, _ptr(c), _ptr(r), float(eps), int(subsample),
                                                    int(mode), _ptr(lam), _ptr(dq)))
         return lam, dq, drho, Stats(st.cycles, st.inner_cycles, st.rel_res0, st.rel_res, st.seconds, rc)
 
@@ -485,28 +494,28 @@ class Solver:
         r = self.zeros() if want_field else None
         out = ctypes.c_double(0.0)
         self._bind_stream()
-        self._check(lib().ccmg_residual(self._h, _ptr(phi), _ptr(f), _ptr(r), ctypes.byref(out)))
+        self._check(self._L.ccmg_residual(self._h, _ptr(phi), _ptr(f), _ptr(r), ctypes.byref(out)))
         return r, out.value
 
     def smooth(self, phi: torch.Tensor, f: torch.Tensor, sweeps: int = 1) -> torch.Tensor:
         phi = self._field(phi, "phi")
         f = self._field(f, "f")
         self._bind_stream()
-        self._check(lib().ccmg_smooth(self._h, _ptr(phi), _ptr(f), int(sweeps)))
+        self._check(self._L.ccmg_smooth(self._h, _ptr(phi), _ptr(f), int(sweeps)))
         return phi
 
     def profile(self, on: bool = True) -> None:
-        self._check(lib().ccmg_profile_enable(self._h, int(on)))
+        self._check(self._L.ccmg_profile_enable(self._h, int(on)))
 
     def profile_read(self, which: int, reset: bool = True) -> Tuple[float, int]:
         ms = ctypes.c_double(0.0)
         n = ctypes.c_int(0)
-        self._check(lib().ccmg_profile_read(self._h, which, ctypes.byref(ms), ctypes.byref(n), int(reset)))
+        self._check(self._L.ccmg_profile_read(self._h, which, ctypes.byref(ms), ctypes.byref(n), int(reset)))
         return ms.value, n.value
 
     def history(self):
         buf = (ctypes.c_double * (MAX_CYCLES + 1))()
-        n = lib().ccmg_history(self._h, buf, MAX_CYCLES + 1)
+        n = self._L.ccmg_history(self._h, buf, MAX_CYCLES + 1)
         return list(buf[:n])
 
 

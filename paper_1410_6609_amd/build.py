@@ -10,6 +10,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "ccmg.hip")
 LIB = os.path.join(HERE, "libccmg.so")
+# a second build with other tile macros, for the test that the iterates do not
+# depend on the tiling: 4-wave FP64 blocks (64x16 loaded tiles, as few as 6
+# owned rows beside the 5-row halos) and 8-wave FP32 blocks (64x32)
+TILES_LIB = os.path.join(HERE, "libccmg_tiles.so")
+TILES_DEFINES = ("CCMG_WAVES=4", "CCMG_WAVES_F32=8")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -35,17 +40,37 @@ HOST_SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsa
                        "-shared-libsan"]
 
 
+def _command(out: str, defines=(), sanitize_host: bool = False):
+    return [hipcc(), *HIPCC_FLAGS, *[f"-D{d}" for d in defines], *(HOST_SANITIZE_FLAGS if sanitize_host else []),
+            "-o", out + ".tmp", SRC]
+
+
 def build(verbose: bool = False, out: str = LIB, defines=(), sanitize_host: bool = False) -> str:
     """Compile libccmg.so; `defines` are extra -D tuning macros (tile shape)."""
-    tmp = out + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *[f"-D{d}" for d in defines], *(HOST_SANITIZE_FLAGS if sanitize_host else []),
-           "-o", tmp, SRC]
+    cmd = _command(out, defines, sanitize_host)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=HERE)
-    os.replace(tmp, out)
+    os.replace(out + ".tmp", out)
     return out
 
 
+def build_all(verbose: bool = False) -> None:
+    """libccmg.so and the other-tiling build beside it, compiled side by side."""
+    jobs = [(LIB, ()), (TILES_LIB, TILES_DEFINES)]
+    procs = []
+    for out, defines in jobs:
+        cmd = _command(out, defines)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd, cwd=HERE))
+    codes = [p.wait() for p in procs]
+    for (out, _), code in zip(jobs, codes):
+        if code != 0:
+            raise subprocess.CalledProcessError(code, out)
+        os.replace(out + ".tmp", out)
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    build_all(verbose="-v" in sys.argv)
+    print(LIB, TILES_LIB)
