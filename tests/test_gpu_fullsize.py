@@ -121,3 +121,32 @@ def test_channel_adjoint_elementwise_parity():
     assert dg64 <= 1e-11 * gs
     assert dl32 <= 1e-9 * ls
     assert dg32 <= 1e-9 * gs
+
+
+def test_largest_grid_2_31_cells():
+    """1024x1024x2048 = 2^31 cells, 17 GB per field (about 75 GB of device
+    memory with the workspace): every cell index past 2^31 must be 64-bit.
+    Deposition counts against the oracle's exactly; the solve from zero reaches
+    1e-10 in the usual cycle count, and the oracle's own FP64 residual of the
+    GPU solution confirms it (a property that holds at any size; a full oracle
+    solve at this size would take minutes)."""
+    w = W.C3.scaled((1024, 1024, 2048), levels=9, n_spheres=16000, name="spheres_1024x1024x2048")
+    log_case("largest grid", w.shape)
+    sph = W.workload_spheres(w)
+    s = make(w)
+    f, cnt = s.deposit(*(to_dev(a) for a in (sph.centers, sph.radii, sph.charges)), counts=True)
+    phi, st = s.solve(f, rtol=w.rtol, zero_guess=True)
+    torch.cuda.synchronize()
+    print(f"2^31 cells: {st.cycles} cycles, rel_res {st.rel_res:.2e}", flush=True)
+    assert st.rel_res < 1e-10 and st.cycles <= 14
+    counts = cnt.cpu().numpy()
+    phi_h = phi.cpu().numpy()
+    del f, phi, s
+    torch.cuda.empty_cache()
+    f_ref, cnt_ref = oracle.deposit(w.shape, w.h, sph.centers, sph.radii, sph.charges)
+    assert np.array_equal(counts, cnt_ref)
+    b = oracle.fold(f_ref, w.h, w.kinds, w.values)
+    del f_ref
+    rel = oracle.norm2(oracle.residual(phi_h, b, w.h, w.kinds)) / oracle.norm2(b)
+    print(f"2^31 cells: oracle's residual of the GPU solution {rel:.3e}", flush=True)
+    assert rel < 1.0001e-10
