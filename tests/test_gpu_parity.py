@@ -184,6 +184,51 @@ def test_tile_geometry_invariance(case, precision):
     assert abs(s1.rel_res - s0.rel_res) <= 1e-13 * s0.rel_res
 
 
+# the smallest and most elongated hierarchies the library accepts: two cells
+# per axis, single-cell and one-cell-wide coarse grids, non-powers of two
+DEGENERATE = [
+    ((2, 2, 2), 2, (D,) * 6),
+    ((4, 2, 8), 2, (N, N, N, N, D, D)),
+    ((256, 2, 2), 2, (D, D, N, N, N, N)),
+    ((2, 2, 512), 2, (N, N, N, N, D, D)),
+    ((6, 10, 4), 2, (D, N, N, D, N, D)),
+    ((128, 4, 2), 2, (D,) * 6),
+    ((2, 64, 64), 2, (N, D, D, N, D, N)),
+    ((8, 8, 1024), 4, (N, N, N, N, D, D)),
+]
+
+
+@pytest.mark.parametrize("case", DEGENERATE, ids=lambda c: "x".join(map(str, c[0])) + f"-L{c[1]}")
+def test_degenerate_shapes_match_oracle(case):
+    """Per-cycle and solve parity on degenerate grids: the FP64 iterates after 3
+    cycles within 1e-12 of the oracle's, the solve to 1e-10 in the oracle's
+    cycle count and within 1e-11 of its solution (the two round differently,
+    fused multiply-adds against none, and over a full solve those differences
+    grow with the conditioning: Dirichlet faces 1024 cells apart give about
+    4 n^2 / pi^2 = 4e5, and 8x8x1024 ends 1.3e-12 apart); FP32 refinement on
+    three of them reaches the FP64 solution."""
+    shape, levels, kinds = case
+    values = (0.2, -0.1, 0.0, 0.3, 1.0, -0.5)
+    log_case("degenerate", shape, levels)
+    h = 1.0 / max(shape)
+    f = rhs(shape, 5)
+    b = oracle.fold(f, h, kinds, values)
+    s = pkg.Solver(shape, h, list(zip(kinds, values)), pkg.Options(levels=levels), device=DEV)
+    phi3, _ = s.solve(to_dev(f), rtol=0.0, max_cycles=3, check=False)
+    ref3, _, _ = oracle.solve(b, h, kinds, levels, rtol=0.0, max_cycles=3)
+    assert np.abs(phi3.cpu().numpy() - ref3).max() <= 1e-12 * np.abs(ref3).max()
+    phi, st = s.solve(to_dev(f), rtol=1e-10)
+    ref, hist, ost = oracle.solve(b, h, kinds, levels, rtol=1e-10)
+    assert ost == 0 and st.cycles == len(hist) - 1 and st.rel_res < 1e-10
+    assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-11 * np.abs(ref).max()
+    if shape in ((2, 2, 2), (6, 10, 4), (8, 8, 1024)):
+        s32 = pkg.Solver(shape, h, list(zip(kinds, values)), pkg.Options(levels=levels, precision=pkg.FP32_IR),
+                         device=DEV)
+        p32, st32 = s32.solve(to_dev(f), rtol=1e-10, zero_guess=True)
+        assert st32.rel_res < 1e-10
+        assert np.abs(p32.cpu().numpy() - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[4]], ids=ids)
 def test_bottom_kernel_matches_pass_path(case):
     """The coarse levels run either as smoother passes plus a separate CG launch
