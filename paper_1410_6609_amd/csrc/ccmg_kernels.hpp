@@ -365,10 +365,6 @@ struct PassShape {
 #define CCMG_PASS_WAVES_PER_EU 1
 #endif
 
-#ifndef CCMG_PARENTS_PER_PLANE
-#define CCMG_PARENTS_PER_PLANE 0
-#endif
-constexpr bool kParentsPerPlane = CCMG_PARENTS_PER_PLANE != 0;
 
 template <typename T, int SPHI, int LOAD, int RES, int M, int WY, bool PAD = false>
 __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassParams<T> P)
@@ -533,7 +529,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
             else { nph[k][r][0] = T(0); nph[k][r][1] = T(0); }
             if constexpr (LOAD == LOAD_CORR) bload2(rc, offL4[r], ncr[k][r][0], ncr[k][r][1]);
         }
-        if constexpr (LOAD == LOAD_PROLONG && (kParentsPerPlane || !decltype(oddt)::value)) load_parents(t, nex[k], tlim);
+        if constexpr (LOAD == LOAD_PROLONG && !decltype(oddt)::value) load_parents(t, nex[k], tlim);
     };
 
     // tbeg has the parity of S (z0 is even); a cross-strip restriction
@@ -546,7 +542,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
         else load_plane(tbeg + k, k, std::false_type{}, tend);
     }
     // the first plane is odd when S is: its parents are those of plane tbeg - 1
-    if constexpr (LOAD == LOAD_PROLONG && (S & 1) && !kParentsPerPlane) load_parents(tbeg - 1, elast, tend);
+    if constexpr (LOAD == LOAD_PROLONG && (S & 1)) load_parents(tbeg - 1, elast, tend);
 
     // PAD: the march runs a whole number of unrolled blocks of U steps; the
     // steps past tend load zeros (size-0 descriptors) and find every stage,
@@ -566,7 +562,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                 // ---- stage 0: the prefetched plane t enters the rings; plane t+PD is requested
                 {
                     const int s0 = q % RP, sb0 = q % RB, k = q % PD;
-                    if constexpr (LOAD == LOAD_PROLONG && !kParentsPerPlane) {
+                    if constexpr (LOAD == LOAD_PROLONG) {
                         if (((S + q) & 1) == 0) {
 #pragma unroll
                             for (int i = 0; i < NE; ++i) elast[i] = nex[k][i];
@@ -576,7 +572,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     for (int r = 0; r < M; ++r) {
                         T v0 = nph[k][r][0], v1 = nph[k][r][1];
                         if constexpr (LOAD == LOAD_PROLONG) {
-                            const T e = kParentsPerPlane ? nex[k][YP ? r : r / 2] : elast[YP ? r : r / 2];
+                            const T e = elast[YP ? r : r / 2];
                             v0 += P.omega * e;
                             v1 += P.omega * e;
                         }
@@ -1090,7 +1086,6 @@ __device__ int cg_one_wave(GetB get_b, PutX put_x, double* rl, int nx, int ny, i
     return it;
 }
 
-constexpr int kCgPad = 10 * 10 * 10 + 64;   // padded cells of the largest one-wave grid shapes, with slack
 
 // Standalone coarsest-grid CG for n <= 512 cells: one wave.
 template <typename T>
