@@ -61,6 +61,28 @@ def test_fp32_ir_zero_guess_any_step_count():
         assert torch.equal(p, p_ref), (k, float((p - p_ref).abs().max()))
 
 
+@pytest.mark.parametrize("zero_guess", [False, True], ids=["solve", "solve_zero"])
+def test_rhs_at_any_alignment(zero_guess):
+    """A caller may pass f at any 8-byte offset: the same right-hand side 8
+    bytes off a 16-byte boundary gives the same iterates bit for bit."""
+    shape, levels, kinds, values = CASES[1]
+    log_case("rhs alignment", shape, zero_guess)
+    s = solver_for(shape, levels, kinds, values)
+    f = to_dev(rhs(shape, 15))
+    nx, ny, nz = shape
+    store = torch.empty(f.numel() + 1, dtype=torch.float64, device=DEV)
+    f_off = store[1:].view(nz, ny, nx)
+    f_off.copy_(f)
+    assert f.data_ptr() % 16 == 0 and f_off.data_ptr() % 16 == 8
+    out = []
+    for ff in (f, f_off):
+        p = s.zeros()
+        _, st = s.solve(ff, p, rtol=1e-10, zero_guess=zero_guess)
+        out.append((p, st))
+    (p0, st0), (p1, st1) = out
+    assert st0.cycles == st1.cycles and torch.equal(p0, p1) and st0.rel_res == st1.rel_res
+
+
 def test_solve_zero_variable_permittivity():
     shape, levels, kinds, values = CASES[1]
     log_case("solve_zero vc", shape)
