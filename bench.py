@@ -117,7 +117,7 @@ def host_cpu() -> dict:
     return {"cpu_model": model, "usable_cores": len(os.sched_getaffinity(0))}
 
 
-def cpu_baseline(w: W.Workload, sph, budget_s: float = 8.0):
+def cpu_baseline(w: W.Workload, sph, budget_s: float = 12.0):
     import oracle
     oracle.lib()
     cores = oracle.num_threads()
@@ -131,7 +131,7 @@ def cpu_baseline(w: W.Workload, sph, budget_s: float = 8.0):
         runs += 1
         cycles = len(hist) - 1
         el = time.perf_counter() - t0
-        if el >= budget_s or runs >= 3:
+        if el >= budget_s or runs >= 4:
             break
     per = el / runs
     return {"value": w.cells / per, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
