@@ -299,3 +299,39 @@ def test_fold_field_constant_arrays_equal_constant_fold(orc, kinds):
     # a face without an array falls back to its constant value
     mixed = [None, faces[1], None, faces[3], faces[4], None]
     assert np.array_equal(orc.fold_field(f, h, kinds, values, mixed), b_const)
+
+
+def test_diagonal_matches_the_paper_centres_and_the_operator(orc):
+    """d_c at boundary cells (Sec. 5.3, the stencil's boundary adaptation):
+    one Dirichlet face gives the centre 7, one Neumann face 5, interior 6, and
+    every face adds its own +1 / -1 (corners of three faces: 9 or 3).  The
+    diagonal also equals h^2 times the operator's dense diagonal, read off by
+    applying the operator to unit vectors."""
+    shape = (4, 6, 4)
+    h = 0.5
+    dd = [D] * 6
+    nn = [N] * 6
+    assert orc.diag_at(shape, dd, 1, 2, 1) == 6
+    assert orc.diag_at(shape, dd, 0, 2, 1) == 7
+    assert orc.diag_at(shape, nn, 0, 2, 1) == 5
+    assert orc.diag_at(shape, dd, 0, 0, 0) == 9
+    assert orc.diag_at(shape, nn, 3, 5, 3) == 3
+    mixed = [D, N, N, D, D, N]
+    nx, ny, nz = shape
+    for k, j, i in itertools.product(range(nz), range(ny), range(nx)):
+        e = np.zeros((nz, ny, nx))
+        e[k, j, i] = 1.0
+        col = orc.apply(e, h, mixed, 0)
+        assert orc.diag_at(shape, mixed, i, j, k) == round(col[k, j, i] * h * h)
+        assert col[k, j, i] * h * h == float(orc.diag_at(shape, mixed, i, j, k))
+
+
+def test_norm2_against_numpy(orc):
+    """The Euclidean norm: numpy's on random vectors, exact on a Pythagorean
+    triple, zero on the zero vector."""
+    rng = np.random.default_rng(3)
+    for n in (1, 7, 4096, 100_000):
+        v = rng.standard_normal(n) * 10.0 ** rng.integers(-3, 4)
+        assert abs(orc.norm2(v) - np.linalg.norm(v)) <= 1e-14 * np.linalg.norm(v)
+    assert orc.norm2(np.array([3.0, 4.0, 12.0])) == 13.0
+    assert orc.norm2(np.zeros(9)) == 0.0
