@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libccmg.so")
 # depend on the tiling: 4-wave FP64 blocks (64x16 loaded tiles, as few as 6
 # owned rows beside the 5-row halos) and 8-wave FP32 blocks (64x32)
 TILES_LIB = os.path.join(HERE, "libccmg_tiles.so")
-TILES_DEFINES = ("CCMG_WAVES=4", "CCMG_WAVES_F32=8")
+TILES_DEFINES = ("CCMG_WAVES=4", "CCMG_WAVES_F32=8", "CCMG_CHUNK_CAPACITY_SCALE=3", "CCMG_PAD_MIN_PLANES=8")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -44,6 +44,16 @@ namespace {
 #ifndef CCMG_WAVES_F32
 #define CCMG_WAVES_F32 16
 #endif
+// Scale of the block capacity that the z-chunk choice assumes, and the chunk
+// length from which the FP64 passes march whole unrolled blocks: both only
+// move work between blocks and code paths (a second build varies them to test
+// that the iterates do not depend on the decomposition)
+#ifndef CCMG_CHUNK_CAPACITY_SCALE
+#define CCMG_CHUNK_CAPACITY_SCALE 1
+#endif
+#ifndef CCMG_PAD_MIN_PLANES
+#define CCMG_PAD_MIN_PLANES 64
+#endif
 constexpr int kM = CCMG_ROWS;
 constexpr int kWY = CCMG_WAVES;
 // waves (strip pairs) per block of the smoother passes, per storage type
@@ -201,7 +211,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // ---------------------------------------------------------------------------
 int g_num_cus = 256;   // set from the device at workspace attachment
 constexpr size_t kBottomMaxLds = 160 * 1024;
-constexpr int kPadMinPlanes = 64;   // z-chunks from which FP64 passes march whole unrolled blocks
+constexpr int kPadMinPlanes = CCMG_PAD_MIN_PLANES;   // z-chunks from which FP64 passes march whole unrolled blocks
 constexpr int kFoldMaxBlocks = 4096;   // grid of the fold (grid-stride over x-rows)
 
 template <typename T, int SPHI, int LOAD, int RES>
@@ -222,7 +232,7 @@ bool launch_one(const PassParams<T>& P0, hipStream_t st)
     }
     static_assert(Sh::H <= kMaxHalo, "halo larger than the partials bound assumes");
     PassParams<T> P = P0;
-    const Grid g = pass_grid(P.nx, P.ny, P.nz, Sh::TX, Sh::TY, Sh::S, g_num_cus * per_cu);
+    const Grid g = pass_grid(P.nx, P.ny, P.nz, Sh::TX, Sh::TY, Sh::S, g_num_cus * per_cu * CCMG_CHUNK_CAPACITY_SCALE);
     P.tiles_x = g.tiles_x;
     P.tiles_y = g.tiles_y;
     P.zchunks = g.zchunks;

@@ -369,6 +369,15 @@ struct PassShape {
 template <typename T, int SPHI, int LOAD, int RES, int M, int WY, bool PAD = false>
 __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassParams<T> P)
 {
+    // No fused multiply-adds formed by the compiler: every stage is unrolled
+    // into U copies and the long marches have a padded variant, and the
+    // compiler's choice to fuse a product with a sum can differ between
+    // copies, so a cell's rounding would depend on the step position at which
+    // its plane is processed, i.e. on where its z-chunk starts.  The fused
+    // forms that matter are written out (the residual d phi - sum with one
+    // rounding, the prolongation and the refinement update), so every cell is
+    // computed the same way under any tiling.
+#pragma clang fp contract(off)
     using Sh = PassShape<T, SPHI, RES, M, WY, LOAD>;
     constexpr int S = Sh::S, H = Sh::H, HY = Sh::HY, YP = Sh::YP, TX = Sh::TX, TY = Sh::TY, RP = Sh::RP, RB = Sh::RB,
                   U = Sh::U;
@@ -573,12 +582,12 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                         T v0 = nph[k][r][0], v1 = nph[k][r][1];
                         if constexpr (LOAD == LOAD_PROLONG) {
                             const T e = elast[YP ? r : r / 2];
-                            v0 += P.omega * e;
-                            v1 += P.omega * e;
+                            v0 = fma(P.omega, e, v0);
+                            v1 = fma(P.omega, e, v1);
                         }
                         if constexpr (LOAD == LOAD_CORR) {
-                            v0 += sig_cur * (T)ncr[k][r][0];
-                            v1 += sig_cur * (T)ncr[k][r][1];
+                            v0 = fma(sig_cur, (T)ncr[k][r][0], v0);
+                            v1 = fma(sig_cur, (T)ncr[k][r][1], v1);
                         }
                         ph[s0][r][0] = v0; ph[s0][r][1] = v1;
                         bb[sb0][r][0] = nbb[k][r][0]; bb[sb0][r][1] = nbb[k][r][1];
@@ -736,7 +745,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                             const T ym = r > 0 ? ph[sc][r - 1][c] : elo[c];
                             const T yp = r < M - 1 ? ph[sc][r + 1][c] : ehi[c];
                             const T sum = ((((xm + xq) + ym) + yp) + ph[sm][r][c]) + ph[sp][r][c];
-                            res[r][c] = bb[sb][r][c] - ((T(dxy[r][c] + dz) + P.shift) * ph[sc][r][c] - sum);
+                            res[r][c] = bb[sb][r][c] - fma(T(dxy[r][c] + dz) + P.shift, ph[sc][r][c], -sum);
                         }
                     }
                     if constexpr (Sh::XSTRIP_RESTRICT) {

@@ -155,14 +155,22 @@ def test_fusion_and_tiling_invariance():
     assert np.array_equal(out[0], out[1])
 
 
+# the parity cases and one grid whose passes march long z-chunks (the padded
+# march in the library, the unpadded one or other chunks in the second build)
+TILE_CASES = CASES + [((128, 128, 128), 5, (D, N, N, D, D, N), (0.2, 0, 0, -0.5, 1.0, 0))]
+
+
 @pytest.mark.parametrize("precision", [pkg.FP64, pkg.FP32_IR], ids=["fp64", "fp32ir"])
-@pytest.mark.parametrize("case", CASES, ids=ids)
+@pytest.mark.parametrize("case", TILE_CASES, ids=ids)
 def test_tile_geometry_invariance(case, precision):
-    """A second build of the same sources with other tile macros (4-wave FP64
-    blocks: 64x16 loaded tiles owning as few as 6 rows beside 5-row halos, so
-    every tile boundary and z chunk moves; 8-wave FP32 blocks) updates every
-    cell from the same operands in the same order: the iterates are bitwise
-    equal, and the norms differ only by the grouping of their block partials."""
+    """A second build of the same sources with other decomposition macros
+    (4-wave FP64 blocks: 64x16 loaded tiles owning as few as 6 rows beside
+    5-row halos; 8-wave FP32 blocks; three times the block capacity in the
+    z-chunk choice, so shorter chunks; the padded march from 8 planes instead
+    of 64), so every tile boundary and z chunk moves and levels change between
+    the padded and the unpadded march, updates every cell from the same
+    operands in the same order: the iterates are bitwise equal, and the norms
+    differ only by the grouping of their block partials."""
     import os
     from paper_1410_6609_amd import build as hipbuild
     if not os.path.exists(hipbuild.TILES_LIB):
