@@ -2364,6 +2364,10 @@ constexpr int kVcPassTY = 2 * kVcPassWaves * kVcPassRows - 2 * 2;   // y halo 2
 template <bool PROLONG>
 __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_pass(VcPassParams P)
 {
+    // No implicit fusion of products and sums (the same reason as in k_pass:
+    // the unrolled copies of a stage must round alike); the fused forms are
+    // written out.
+#pragma clang fp contract(off)
     using T = double;
     constexpr int M = kVcPassRows, WY = kVcPassWaves, S = 2, H = 2, HY = 2;
     constexpr int NSTRIP = 2 * WY, TX = kVcPassTX, TY = kVcPassTY;
@@ -2496,7 +2500,7 @@ __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_pass(VcPassParams P
                     for (int r = 0; r < M; ++r) {
 #pragma unroll
                         for (int c = 0; c < 2; ++c) {
-                            ph[s0][r][c] = PROLONG ? nph[r][c] + P.omega * elast : nph[r][c];
+                            ph[s0][r][c] = PROLONG ? fma(P.omega, elast, nph[r][c]) : nph[r][c];
                             fz[sf0][r][c] = nfz[r][c];
                         }
                     }
@@ -2540,18 +2544,18 @@ __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_pass(VcPassParams P
                         const T kym = fy[sf][r][o], kyp = fy[sf][r + 1][o];
                         const T kzm = fz[sf][r][o], kzp = fz[sfp][r][o];
                         T dd = (o == 0 ? wx0 : T(1)) * kxm;
-                        dd += (o == 1 ? wx1 : T(1)) * kxp;
-                        dd += (r == 0 ? wy0 : T(1)) * kym;
-                        dd += (r == 1 ? wy1 : T(1)) * kyp;
-                        dd += wzm * kzm;
-                        dd += wzp * kzp;
+                        dd = fma(o == 1 ? wx1 : T(1), kxp, dd);
+                        dd = fma(r == 0 ? wy0 : T(1), kym, dd);
+                        dd = fma(r == 1 ? wy1 : T(1), kyp, dd);
+                        dd = fma(wzm, kzm, dd);
+                        dd = fma(wzp, kzp, dd);
                         // neighbours outside the domain are zero: their terms add nothing
                         T ss = kxm * xm;
-                        ss += kxp * xq;
-                        ss += kym * ym;
-                        ss += kyp * yq;
-                        ss += kzm * ph[sm][r][o];
-                        ss += kzp * ph[sp][r][o];
+                        ss = fma(kxp, xq, ss);
+                        ss = fma(kym, ym, ss);
+                        ss = fma(kyp, yq, ss);
+                        ss = fma(kzm, ph[sm][r][o], ss);
+                        ss = fma(kzp, ph[sp][r][o], ss);
                         const T nv = (bb[sf][r][o] + ss) / dd;
                         ph[sc][r][o] = vrow[r] ? nv : T(0);   // cells outside the domain have d = 0
                     }
@@ -2599,6 +2603,10 @@ struct VcResParams {
 template <bool RESTRICT>
 __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_res(VcResParams P)
 {
+    // No implicit fusion of products and sums (the same reason as in k_pass:
+    // the unrolled copies of a stage must round alike); the fused forms are
+    // written out.
+#pragma clang fp contract(off)
     using T = double;
     constexpr int M = kVcPassRows, WY = kVcPassWaves, S = 1, H = 2, HY = 2;
     constexpr int NSTRIP = 2 * WY, TX = kVcPassTX, TY = kVcPassTY;
@@ -2751,18 +2759,18 @@ __global__ __launch_bounds__(64 * kVcPassWaves, 1) void k_vc_res(VcResParams P)
                             const T kym = fy[sf][r][o], kyp = fy[sf][r + 1][o];
                             const T kzm = fz[szm][r][o], kzp = fz[szp][r][o];
                             T dd = (o == 0 ? wx0 : T(1)) * kxm;
-                            dd += (o == 1 ? wx1 : T(1)) * kxp;
-                            dd += (r == 0 ? wy0 : T(1)) * kym;
-                            dd += (r == 1 ? wy1 : T(1)) * kyp;
-                            dd += wzm * kzm;
-                            dd += wzp * kzp;
+                            dd = fma(o == 1 ? wx1 : T(1), kxp, dd);
+                            dd = fma(r == 0 ? wy0 : T(1), kym, dd);
+                            dd = fma(r == 1 ? wy1 : T(1), kyp, dd);
+                            dd = fma(wzm, kzm, dd);
+                            dd = fma(wzp, kzp, dd);
                             T ss = kxm * xm;
-                            ss += kxp * xq;
-                            ss += kym * ym;
-                            ss += kyp * yq;
-                            ss += kzm * ph[sm][r][o];
-                            ss += kzp * ph[sp][r][o];
-                            res[r][o] = bb[sf][r][o] - (dd * ph[sc][r][o] - ss);
+                            ss = fma(kxp, xq, ss);
+                            ss = fma(kym, ym, ss);
+                            ss = fma(kyp, yq, ss);
+                            ss = fma(kzm, ph[sm][r][o], ss);
+                            ss = fma(kzp, ph[sp][r][o], ss);
+                            res[r][o] = bb[sf][r][o] - fma(dd, ph[sc][r][o], -ss);
                         }
                     }
                     if constexpr (RESTRICT) {
