@@ -634,7 +634,7 @@ int launch_vc_res(ccmg_solver* s, int l, const double* phi, double* bc_out, doub
         per_cu = nb;
     }
     const LevelBuf& B = s->lv[l];
-    const Grid g = pass_grid(B.nx, B.ny, B.nz, kVcPassTX, kVcPassTY, 2, g_num_cus * per_cu);
+    const Grid g = pass_grid(B.nx, B.ny, B.nz, kVcPassTX, kVcPassTY, 2, g_num_cus * per_cu * CCMG_CHUNK_CAPACITY_SCALE);
     if (!RESTRICT && g.blocks() > s->max_partials) return 0;
     VcResParams P;
     std::memset(&P, 0, sizeof P);
@@ -713,7 +713,7 @@ void enqueue_vc_smooth(ccmg_solver* s, int l, double* home, int sweeps, const do
         }
         per_cu = nb;
     }
-    const Grid g = pass_grid(B.nx, B.ny, B.nz, kVcPassTX, kVcPassTY, 2, g_num_cus * per_cu);
+    const Grid g = pass_grid(B.nx, B.ny, B.nz, kVcPassTX, kVcPassTY, 2, g_num_cus * per_cu * CCMG_CHUNK_CAPACITY_SCALE);
     VcPassParams P;
     std::memset(&P, 0, sizeof P);
     P.L = vc_level(s, l);

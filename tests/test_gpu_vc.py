@@ -81,6 +81,33 @@ def test_vc_solve_parity(case):
     assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("case", VC_CASES, ids=ids)
+def test_vc_tile_geometry_invariance(case):
+    """The stored-stencil passes under another z-chunking (the second build of
+    the same sources, which assumes three times the block capacity when it
+    chooses the chunks): every cell is updated from the same operands in the
+    same order, so the iterates are bitwise equal."""
+    import os
+    from paper_1410_6609_amd import build as hipbuild
+    if not os.path.exists(hipbuild.TILES_LIB):
+        pytest.fail(f"{hipbuild.TILES_LIB} is missing: run __graft_entry__.build()")
+    shape, levels, kinds, values = case
+    log_case("vc tile geometry", shape)
+    h = 1.0 / shape[0]
+    eps = to_dev(lognormal_eps(shape, 4))
+    f = to_dev(rhs(shape, 6))
+    out = []
+    for library in (None, pkg.load_library(hipbuild.TILES_LIB)):
+        s = pkg.Solver(shape, h, list(zip(kinds, values)), pkg.Options(levels=levels, variable_eps=1), device=DEV,
+                       library=library)
+        s.set_permittivity(eps)
+        phi, st = s.solve(f, rtol=0.0, max_cycles=3, check=False)
+        torch.cuda.synchronize()
+        out.append(phi.cpu().numpy())
+        del s
+    assert np.array_equal(out[0], out[1]), float(np.abs(out[0] - out[1]).max())
+
+
 def test_vc_jumping_permittivity_spheres():
     """Dielectric spheres (eps 2.5) in a fluid (eps 78.5) carrying the charges."""
     w = W.C2.scaled((64, 64, 64), levels=4, n_spheres=30)
