@@ -562,11 +562,27 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
     // loses its prefetch (the finest post-smoothing pass ran 10 % slower),
     // while a short one (coarse levels) would lose more to the padding.
     const int tstop = PAD ? tbeg + U * ((tend - tbeg + U - 1) / U) : tend;
+    // Two copies of the unrolled block of U steps: blocks whose steps all lie
+    // in [max(z0, 1) + S + 1, min(z1 + SPHI, nz)) run a copy with CK = false,
+    // where every stage's plane is inside its needed range and the domain and
+    // off the z faces, and the output, residual and restriction planes inside
+    // the chunk, so those tests (scalar compares, selects and branches in
+    // every stage) are compiled out; the other blocks run the checked copy.
+    // The arithmetic is the same in both.  Long marches only: the padded ones
+    // and the single-stage FP64 passes (the second copy costs registers, which
+    // the FP32 and the short five-stage passes do not have to spare).
+    const int t_lo = max(z0, 1) + S + 1, t_hi = min(z1 + SPHI, nz);
+    constexpr int NCOPY = (PAD || (sizeof(T) == 8 && SPHI == 0)) ? 2 : 1;
     for (int tb = tbeg; tb < tstop; tb += U) {
+    const bool interior = NCOPY == 2 && tb >= t_lo && tb + U <= t_hi;
+#pragma unroll
+    for (int copy = 0; copy < NCOPY; ++copy) {
+    const bool CK = NCOPY == 1 || copy == 1;
+    if (NCOPY == 2 && (copy == 0) != interior) continue;
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int t = tb + q;
-            if (PAD || t < tend) {
+            if (!CK || PAD || t < tend) {
                 const int par = t & 1;
                 // ---- stage 0: the prefetched plane t enters the rings; plane t+PD is requested
                 {
@@ -644,16 +660,16 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     const int cs = (s + 1) & 1;
                     const int ppar = (S + q - s) & 1;
                     int dz = 0;
-                    if (p == 0) dz += P.sh[4];
-                    if (p == nz - 1) dz += P.sh[5];
+                    if (CK && p == 0) dz += P.sh[4];
+                    if (CK && p == nz - 1) dz += P.sh[5];
                     // Stage s is needed on planes [z0 - (S - s), z1 + (S - s)); outside, its
                     // values are read only by later stages that are skipped as well
                     // (the needed ranges nest), so the halo steps at the chunk ends run
                     // only the stages that matter.  Planes outside the domain are skipped
                     // too (see SKIP_OUTSIDE): they were loaded as zeros and must stay zero.
-                    if (p < z0 - (S - s) || p >= z1 + (S - s)) continue;
+                    if (CK && (p < z0 - (S - s) || p >= z1 + (S - s))) continue;
                     const bool pin = (p >= 0) && (p < nz);
-                    if (Sh::SKIP_OUTSIDE && !pin) continue;
+                    if (CK && Sh::SKIP_OUTSIDE && !pin) continue;
                     const T elo = e_lo[s - 1];
                     const T ehi = e_hi[s - 1];
                     // 1/diagonal of the updated cell of each row; planes at a z face
@@ -662,7 +678,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     T invz[M];
 #pragma unroll
                     for (int r = 0; r < M; ++r) invz[r] = inv0[r][(cs + r + ppar + YP) & 1];
-                    if (dz != 0) {
+                    if (CK && dz != 0) {
 #pragma unroll
                         for (int r = 0; r < M; ++r) {
                             const int o = (cs + r + ppar + YP) & 1;
@@ -681,7 +697,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                         // cells outside the domain have 1/d = 0: they stay zero
                         const T nv = (bb[sb][r][o] + sum) * invz[r];
                         if constexpr (Sh::SKIP_OUTSIDE) ph[sc][r][o] = nv;
-                        else ph[sc][r][o] = pin ? nv : T(0);
+                        else ph[sc][r][o] = (!CK || pin) ? nv : T(0);
                     }
                     // keep the stages apart in the schedule (bounds register live ranges)
                     __builtin_amdgcn_sched_barrier(0);
@@ -699,7 +715,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                 // ---- output of the smoothed plane t - SPHI
                 if (P.phi_out != nullptr) {
                     const int po = t - SPHI;
-                    if (po >= z0 && po < z1) {
+                    if (!CK || (po >= z0 && po < z1)) {
                         const int so = (q - SPHI + 2 * U) % RP;
                         const auto rs = plane_rsrc(P.phi_out, planeB, po, true);
 #pragma unroll
@@ -709,7 +725,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                 // ---- restriction across strips of the plane whose residual the
                 // previous step computed: children rows y (this thread's row 1) and
                 // y + 1 (the next strip's row 0), planes paired in z as above
-                if constexpr (Sh::XSTRIP_RESTRICT) if (t - 1 - S >= z0 && t - 1 - S < z1) {
+                if constexpr (Sh::XSTRIP_RESTRICT) if (!CK || (t - 1 - S >= z0 && t - 1 - S < z1)) {
                     const int pp = t - 1 - S;
                     const T q0n = rq[par ^ 1][strip + 1][xp];             // the pad after the last strip
                     const T s4 = q1p + q0n;
@@ -721,16 +737,16 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                     }
                 }
                 // ---- residual stage at plane t - S (both cells of every pair)
-                if constexpr (RES != RES_NONE) if (t - S >= z0 && t - S < z1) {
+                if constexpr (RES != RES_NONE) if (!CK || (t - S >= z0 && t - S < z1)) {
                     const int p = t - S;
                     const int sc = (q - S + 2 * U) % RP;
                     const int sm = (q - S - 1 + 2 * U) % RP;
                     const int sp = (q - S + 1 + 2 * U) % RP;
                     const int sb = (q - S + 2 * U) % RB;
-                    const bool pok = (p >= z0) && (p < z1);
+                    const bool pok = !CK || ((p >= z0) && (p < z1));
                     int dz = 0;
-                    if (p == 0) dz += P.sh[4];
-                    if (p == nz - 1) dz += P.sh[5];
+                    if (CK && p == 0) dz += P.sh[4];
+                    if (CK && p == nz - 1) dz += P.sh[5];
                     const T* elo = e2lo;
                     const T* ehi = e2hi;
                     T res[M][2];
@@ -788,6 +804,7 @@ __global__ __launch_bounds__(64 * WY, CCMG_PASS_WAVES_PER_EU) void k_pass(PassPa
                 __syncthreads();
             }
         }
+    }
     }
 
     if constexpr (RES == RES_NORM || RES == RES_NORM_R32 || RES == RES_STORE) {
